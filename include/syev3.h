@@ -1,0 +1,218 @@
+/*
+ * syev3.h -- batched solver for 3x3 real symmetric eigenproblems on AMD
+ * Instinct MI355X (gfx950).  C ABI.
+ *
+ * Method: C. F. Borges, "Solving the 3x3 Real Symmetric Eigenproblem"
+ * (arXiv:1806.06698).  Each matrix is reduced by a Jacobi rotation in the
+ * (1,2)-plane to an ordered arrow (Sec. 1), tested for beta-, combo- and
+ * numerical deflation with a Givens rotation (Sec. 1.1), and otherwise
+ * solved through the two shifted fully reduced arrows: the rightmost zero of
+ * each spectral function by the Borges-Gragg zero finder (Sec. 1.4.1), the
+ * middle eigenvalue by the trace identity and the eigenvectors by the
+ * closed forms u1, u3 and u2 (Sec. 1.2).  The problem solved is the one the
+ * paper's accuracy measures define (Sec. 1.5): for each symmetric A find the
+ * diagonal Lambda and orthonormal V with A V = V Lambda.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * A matrix is given by its 6 unique entries in the order
+ *     a11, a12, a13, a22, a23, a33.
+ * Layouts:
+ *   SYEV3_SOA  structure of arrays.  Entry k of matrix i is A[k*ld + i]
+ *              (6 planes); eigenvalue j is lambda[j*ld + i] (3 planes);
+ *              V[(3*r + c)*ld + i] is row r of eigenvector c (9 planes).
+ *              ld >= n is the plane stride in elements (0 means n).
+ *   SYEV3_AOS  array of structures, packed: A[6*i + k], lambda[3*i + j],
+ *              V[9*i + 3*r + c] (row-major 3x3, column c is eigenvector c,
+ *              as torch.linalg.eigh).  ld must be 0.
+ * Eigenvalues are in ascending order; column c of V belongs to lambda c.
+ * The sign of each eigenvector, and the basis inside an eigenspace of a
+ * repeated eigenvalue, are whatever the method produces.
+ * dtype SYEV3_F64: every array is double.  dtype SYEV3_F32_REFINE: every
+ * array is float; the arithmetic is mixed (see below).
+ * V may be NULL: eigenvalues only.
+ *
+ * Memory: every pointer is device memory owned by the caller, alive until
+ * the work queued on `stream` has finished.  The library allocates nothing
+ * on these paths.  Outputs must not overlap the input or each other.
+ *
+ * Execution: asynchronous on `stream` (a hipStream_t of the current device;
+ * NULL is the null stream).  A return of 0 means the work was enqueued.
+ *
+ * Errors: negative return values, listed below, with nothing enqueued.
+ * n == 0 is a no-op returning 0.  Numerical trouble in one matrix never fails
+ * a call: a matrix with a NaN or infinite entry gets NaN eigenvalues and
+ * eigenvectors.  No C++ exception crosses this interface.  Calls may be made
+ * from several host threads at once; the library keeps no mutable global
+ * state on these paths.
+ */
+#ifndef SYEV3_H
+#define SYEV3_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* dtypes */
+#define SYEV3_F64 0          /* FP64 storage, FP64 arithmetic */
+#define SYEV3_F32_REFINE 1   /* FP32 storage; FP64 reduction, deflation test
+                                and eigenvectors, FP32 zero finder followed
+                                by one FP64 Newton step per root */
+
+/* layouts */
+#define SYEV3_SOA 0
+#define SYEV3_AOS 1
+
+/* flags for batched_syev3_ex */
+#define SYEV3_FLAG_SIMPLIFIED_DEFLATION 1u /* the simplified test of Sec. 1.1,
+                                              |e| <= eps |alpha1 + alpha2|,
+                                              instead of the EISPACK form */
+#define SYEV3_FLAG_NO_H_GUARD 2u  /* treat only h == 0 as diagonal (Sec. 1.1
+                                     literally); by default h <= eps (|alpha1|
+                                     + |alpha2| + |gamma|) also is */
+#define SYEV3_FLAG_NEWTON 4u      /* Newton's method from the left
+                                     (Sec. 1.4.2) instead of Borges-Gragg;
+                                     SYEV3_F64 only */
+#define SYEV3_FLAGS_ALL 7u
+
+/* error codes */
+#define SYEV3_OK 0
+#define SYEV3_E_N (-1)        /* n < 0, or n too large for the layout */
+#define SYEV3_E_NULL (-2)     /* A or lambda is NULL (with n > 0) */
+#define SYEV3_E_DTYPE (-3)    /* unknown dtype, or a flag the dtype lacks */
+#define SYEV3_E_LAYOUT (-4)   /* unknown layout, or bad ld */
+#define SYEV3_E_ALIAS (-5)    /* an output overlaps the input or another
+                                 output */
+#define SYEV3_E_HIP (-6)      /* the HIP runtime refused the launch */
+#define SYEV3_E_FLAGS (-7)    /* unknown flag bits */
+#define SYEV3_E_BUDGET (-8)   /* server: request larger than the HBM budget */
+#define SYEV3_E_AGAIN (-9)    /* server: no room now; retry after a release */
+#define SYEV3_E_STATE (-10)   /* server: bad handle or request state */
+#define SYEV3_E_TIMEOUT (-11) /* server: wait timed out */
+
+/*
+ * batched_syev3 -- eigenvalues (and eigenvectors if V != NULL) of n
+ * symmetric 3x3 matrices in structure-of-arrays layout with ld = n.
+ * Same as batched_syev3_ex(n, A, 0, SYEV3_SOA, lambda, V, dtype, 0, stream).
+ */
+int batched_syev3(int64_t n, const void* A_upper6, void* lambda, void* V,
+                  int dtype, hipStream_t stream);
+
+/*
+ * batched_syev3_ex -- full form: any layout, plane stride ld (SoA), flags.
+ */
+int batched_syev3_ex(int64_t n, const void* A, int64_t ld, int layout,
+                     void* lambda, void* V, int dtype, uint32_t flags,
+                     hipStream_t stream);
+
+/*
+ * batched_syev3_info -- batched_syev3_ex that also writes, per matrix,
+ * info[i] = branch | (iterations for mu) << 8 | (iterations for nu) << 16,
+ * branch: 0 zero matrix, 1 non-finite input, 2 diagonal arrow (h negligible),
+ * 3 deflated (Sec. 1.1), 4 ordered and reduced (Sec. 1.2); iterations are the
+ * spectral-function evaluations of the zero finder (Sec. 1.4).  info is
+ * device memory of n int32 values.  Used to measure iteration counts.
+ */
+int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
+                       void* lambda, void* V, int dtype, uint32_t flags,
+                       int32_t* info, hipStream_t stream);
+
+/* Text for an error code (static storage). */
+const char* syev3_strerror(int code);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int syev3_version(void);
+
+/*
+ * ------------------------------------------------------------------------
+ * Serving: continuous batching of independent requests.
+ *
+ * A server owns one device pool of `hbm_budget_bytes`.  A client asks for a
+ * request of n matrices of a dtype (syev3_server_acquire); the server admits
+ * it if its input and output buffers fit in the pool and a request slot is
+ * free, and returns device pointers into the pool (SoA layout, ld = n).  The
+ * client writes A (on any stream; it must be complete before submit) and
+ * calls syev3_server_submit.  A scheduler thread gathers every submitted
+ * request into the next tick: one launch of a persistent kernel that walks a
+ * device table of the tick's requests (mixed dtypes) and solves them with the
+ * same per-matrix arithmetic as batched_syev3, so each result is bitwise the
+ * same alone and in any mix.  Up to `max_inflight_ticks` ticks run at once on
+ * separate streams, so requests that arrive while others are on the GPU start
+ * without waiting for them.  Completion is detected by events; then
+ * syev3_server_poll reports the request done and its outputs are readable.
+ * syev3_server_release returns the request's memory to the pool, which admits
+ * waiting requests.  Ticks are launched through HIP graphs captured once per
+ * table slot.
+ * ------------------------------------------------------------------------
+ */
+typedef struct syev3_server syev3_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes;   /* device pool size (request buffers) */
+  int32_t max_requests;        /* request slots (admitted, not released) */
+  int32_t max_inflight_ticks;  /* ticks on the GPU at once (streams) */
+  int32_t max_segments_per_tick; /* requests per tick */
+  int32_t grid_blocks;         /* blocks of the persistent kernel; 0 = auto */
+  int32_t use_graphs;          /* 1: launch ticks through captured graphs */
+} syev3_server_opts;
+
+typedef struct {
+  void* A;        /* device, 6 planes of n (SoA, ld = n), dtype elements */
+  void* lambda;   /* device, 3 planes of n */
+  void* V;        /* device, 9 planes of n, or NULL if vals-only */
+  int64_t n;
+  int32_t dtype;
+} syev3_request_buffers;
+
+typedef struct {
+  int64_t submitted, completed, ticks;
+  int64_t matrices_completed;
+  uint64_t pool_bytes_in_use, pool_bytes_peak;
+  int32_t requests_waiting_admission_peak;
+  int32_t inflight_ticks_peak;
+  double busy_seconds;         /* wall time with at least one tick on the GPU */
+} syev3_server_stats;
+
+/* Defaults: 64 GiB pool, 4096 slots, 4 ticks in flight, 256 segments/tick,
+ * auto grid, graphs on. */
+void syev3_server_default_opts(syev3_server_opts* opts);
+
+/* Create a server on the current device.  Allocates the pool and starts the
+ * scheduler thread.  *out receives the handle. */
+int syev3_server_create(const syev3_server_opts* opts, syev3_server** out);
+
+/* Stop the scheduler (after in-flight ticks finish) and free everything. */
+int syev3_server_destroy(syev3_server* s);
+
+/* Admit a request of n matrices (vals+vecs if want_vectors) of dtype.
+ * Returns a request id >= 0 and fills *bufs, or SYEV3_E_AGAIN if the pool or
+ * the slots are full now, or SYEV3_E_BUDGET if it can never fit. */
+int64_t syev3_server_acquire(syev3_server* s, int64_t n, int dtype,
+                             int want_vectors, syev3_request_buffers* bufs);
+
+/* Queue an admitted request for the next tick.  Its A must be complete. */
+int syev3_server_submit(syev3_server* s, int64_t request);
+
+/* 1 if the request's results are complete, 0 if not yet, < 0 on error.
+ * If done and latency_s is not NULL, it receives submit-to-completion time
+ * in seconds. */
+int syev3_server_poll(syev3_server* s, int64_t request, double* latency_s);
+
+/* Block until the request completes or timeout_s passes (< 0: no limit). */
+int syev3_server_wait(syev3_server* s, int64_t request, double timeout_s,
+                      double* latency_s);
+
+/* Return the request's buffers to the pool (after it completed). */
+int syev3_server_release(syev3_server* s, int64_t request);
+
+int syev3_server_get_stats(syev3_server* s, syev3_server_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYEV3_H */

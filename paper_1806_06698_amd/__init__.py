@@ -1,0 +1,117 @@
+"""Batched 3x3 real symmetric eigensolver for AMD MI355X (gfx950).
+
+The solver is libsyev3.so (hand-written HIP kernels behind a C ABI, see
+include/syev3.h); this package is a thin binding that hands it torch device
+tensors and the current HIP stream.  Method: Borges, "Solving the 3x3 Real
+Symmetric Eigenproblem" (arXiv:1806.06698).
+
+    import torch, paper_1806_06698_amd as s3
+    A = torch.randn(6, n, dtype=torch.float64, device="cuda")   # a11 a12 a13 a22 a23 a33
+    lam, V = s3.syev3(A)          # lam (3, n) ascending; V (9, n): V[3r+c] = row r of vector c
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (AOS, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD,
+                   FLAG_SIMPLIFIED_DEFLATION, SOA, Syev3Error)
+
+__all__ = ["syev3", "batched_syev3", "batched_syev3_ex", "batched_syev3_info",
+           "F64", "F32_REFINE", "SOA", "AOS", "FLAG_SIMPLIFIED_DEFLATION",
+           "FLAG_NO_H_GUARD", "FLAG_NEWTON", "Syev3Error", "lib_path"]
+
+lib_path = _lib.LIB_PATH
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def batched_syev3(n, A_ptr, lam_ptr, V_ptr, dtype, stream_handle) -> int:
+    """Raw C entry point with integer device pointers; returns the status."""
+    return _lib.lib().batched_syev3(n, A_ptr, lam_ptr, V_ptr, dtype, stream_handle)
+
+
+def batched_syev3_ex(n, A_ptr, ld, layout, lam_ptr, V_ptr, dtype, flags,
+                     stream_handle) -> int:
+    return _lib.lib().batched_syev3_ex(n, A_ptr, ld, layout, lam_ptr, V_ptr,
+                                       dtype, flags, stream_handle)
+
+
+def batched_syev3_info(n, A_ptr, ld, layout, lam_ptr, V_ptr, dtype, flags,
+                       info_ptr, stream_handle) -> int:
+    return _lib.lib().batched_syev3_info(n, A_ptr, ld, layout, lam_ptr, V_ptr,
+                                         dtype, flags, info_ptr, stream_handle)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32_REFINE
+    raise TypeError(f"A must be float64 or float32, got {t.dtype}")
+
+
+def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
+          flags: int = 0, info: bool = False, out=None, stream=None):
+    """Eigen-decompose a batch of symmetric 3x3 matrices on the GPU.
+
+    layout "soa": A has shape (6, n), rows a11 a12 a13 a22 a23 a33, row
+    stride ld >= n (a slice of a (6, ld) buffer is fine).  Returns lam (3, n)
+    and V (9, n) with V[3*r + c, i] = row r of eigenvector c of matrix i.
+    layout "aos": A has shape (n, 6), contiguous.  Returns lam (n, 3) and
+    V (n, 3, 3) with columns the eigenvectors (as torch.linalg.eigh).
+    float64 input runs the FP64 path; float32 input the FP32-storage path
+    with FP64 refinement.  vectors=False skips V.  info=True also returns the
+    per-matrix branch and iteration counts (int32).
+    out: optional (lam, V) tensors to write into (same shapes as returned,
+    with the input's ld for SoA).
+    """
+    if not A.is_cuda:
+        raise ValueError("A must be a GPU tensor (the solver has no CPU path)")
+    dt = _dtype_code(A)
+    if layout == "soa":
+        if A.dim() != 2 or A.shape[0] != 6 or A.stride(1) != 1:
+            raise ValueError("SoA input must have shape (6, n) with unit column stride")
+        n = A.shape[1]
+        ld = A.stride(0) if n > 0 else 0
+        if out is None:
+            lam_buf = torch.empty((3, max(ld, 1)), dtype=A.dtype, device=A.device)
+            V_buf = (torch.empty((9, max(ld, 1)), dtype=A.dtype, device=A.device)
+                     if vectors else None)
+            lam, V = lam_buf[:, :n], (V_buf[:, :n] if vectors else None)
+        else:
+            lam, V = out
+            if lam.stride(0) != ld or (V is not None and V.stride(0) != ld):
+                raise ValueError("output plane stride must equal the input's")
+        lay = SOA
+    elif layout == "aos":
+        if A.dim() != 2 or A.shape[1] != 6 or not A.is_contiguous():
+            raise ValueError("AoS input must be a contiguous (n, 6) tensor")
+        n = A.shape[0]
+        ld = 0
+        if out is None:
+            lam = torch.empty((n, 3), dtype=A.dtype, device=A.device)
+            V = torch.empty((n, 3, 3), dtype=A.dtype, device=A.device) if vectors else None
+        else:
+            lam, V = out
+        lay = AOS
+    else:
+        raise ValueError(f"unknown layout {layout!r}")
+    inf = torch.empty(n, dtype=torch.int32, device=A.device) if info else None
+    rc = _lib.lib().batched_syev3_info(
+        n, _ptr(A), ld, lay, _ptr(lam), _ptr(V), dt, flags, _ptr(inf),
+        _stream_handle(stream))
+    _lib.check(rc, "batched_syev3_info")
+    if info:
+        return lam, V, inf
+    return lam, V

@@ -1,0 +1,114 @@
+// syev3_api.cpp -- C ABI of the batched solver: argument checks, then one
+// kernel launch on the caller's stream.  See include/syev3.h.
+#include "syev3.h"
+
+#include <stdint.h>
+
+#include "syev3_internal.hpp"
+
+namespace {
+
+struct Range {
+  uintptr_t lo, hi;  // [lo, hi) in bytes; hi == lo for an absent array
+};
+
+bool overlap(const Range& a, const Range& b) {
+  return a.lo < a.hi && b.lo < b.hi && a.lo < b.hi && b.lo < a.hi;
+}
+
+// Bytes spanned by `planes` planes of n elements at stride ld (SoA) or by
+// n*planes packed elements (AoS).
+Range span(const void* p, int64_t n, int64_t ld, int layout, int planes,
+           size_t esize) {
+  Range r{(uintptr_t)p, (uintptr_t)p};
+  if (!p || n == 0) return r;
+  uint64_t elems = layout == SYEV3_SOA ? (uint64_t)(planes - 1) * (uint64_t)ld + (uint64_t)n
+                                       : (uint64_t)planes * (uint64_t)n;
+  r.hi = r.lo + elems * esize;
+  return r;
+}
+
+int check_args(int64_t n, const void* A, int64_t& ld, int layout,
+               const void* lambda, const void* V, int dtype, uint32_t flags) {
+  if (dtype != SYEV3_F64 && dtype != SYEV3_F32_REFINE) return SYEV3_E_DTYPE;
+  if (flags & ~SYEV3_FLAGS_ALL) return SYEV3_E_FLAGS;
+  if ((flags & SYEV3_FLAG_NEWTON) && dtype != SYEV3_F64) return SYEV3_E_DTYPE;
+  if (layout != SYEV3_SOA && layout != SYEV3_AOS) return SYEV3_E_LAYOUT;
+  if (n < 0) return SYEV3_E_N;
+  // every element index (at most 9 planes of ld) must fit in int64 bytes
+  const int64_t max_elems = (int64_t)(INT64_MAX / 16 / 9);
+  if (layout == SYEV3_SOA) {
+    if (ld == 0) ld = n;
+    if (ld < n || ld > max_elems) return SYEV3_E_LAYOUT;
+  } else {
+    if (ld != 0) return SYEV3_E_LAYOUT;
+    if (n > max_elems) return SYEV3_E_N;
+  }
+  // the grid has one workgroup per 256 matrices
+  if ((n + syev3::kBlock - 1) / syev3::kBlock > (int64_t)UINT32_MAX) return SYEV3_E_N;
+  if (n == 0) return SYEV3_OK;
+  if (!A || !lambda) return SYEV3_E_NULL;
+  const size_t es = dtype == SYEV3_F64 ? sizeof(double) : sizeof(float);
+  const Range ra = span(A, n, ld, layout, 6, es);
+  const Range rl = span(lambda, n, ld, layout, 3, es);
+  const Range rv = span(V, n, ld, layout, 9, es);
+  if (overlap(ra, rl) || overlap(ra, rv) || overlap(rl, rv)) return SYEV3_E_ALIAS;
+  return SYEV3_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
+                       void* lambda, void* V, int dtype, uint32_t flags,
+                       int32_t* info, hipStream_t stream) {
+  const int rc = check_args(n, A, ld, layout, lambda, V, dtype, flags);
+  if (rc != SYEV3_OK || n == 0) return rc;
+  if (info) {
+    const Range ri{(uintptr_t)info, (uintptr_t)info + (uintptr_t)n * sizeof(int32_t)};
+    const size_t es = dtype == SYEV3_F64 ? sizeof(double) : sizeof(float);
+    if (overlap(ri, span(A, n, ld, layout, 6, es)) ||
+        overlap(ri, span(lambda, n, ld, layout, 3, es)) ||
+        overlap(ri, span(V, n, ld, layout, 9, es)))
+      return SYEV3_E_ALIAS;
+  }
+  const hipError_t e = syev3::launch_batched(n, A, ld, layout, lambda, V, dtype,
+                                             flags, info, stream);
+  return e == hipSuccess ? SYEV3_OK : SYEV3_E_HIP;
+}
+
+int batched_syev3_ex(int64_t n, const void* A, int64_t ld, int layout,
+                     void* lambda, void* V, int dtype, uint32_t flags,
+                     hipStream_t stream) {
+  return batched_syev3_info(n, A, ld, layout, lambda, V, dtype, flags, nullptr,
+                            stream);
+}
+
+int batched_syev3(int64_t n, const void* A_upper6, void* lambda, void* V,
+                  int dtype, hipStream_t stream) {
+  return batched_syev3_info(n, A_upper6, 0, SYEV3_SOA, lambda, V, dtype, 0u,
+                            nullptr, stream);
+}
+
+const char* syev3_strerror(int code) {
+  switch (code) {
+    case SYEV3_OK: return "success";
+    case SYEV3_E_N: return "invalid matrix count n";
+    case SYEV3_E_NULL: return "null pointer for a required array";
+    case SYEV3_E_DTYPE: return "unknown dtype, or a flag the dtype does not support";
+    case SYEV3_E_LAYOUT: return "unknown layout or invalid leading dimension";
+    case SYEV3_E_ALIAS: return "an output overlaps the input or another output";
+    case SYEV3_E_HIP: return "HIP runtime error at kernel launch";
+    case SYEV3_E_FLAGS: return "unknown flag bits";
+    case SYEV3_E_BUDGET: return "request larger than the server's HBM budget";
+    case SYEV3_E_AGAIN: return "server full; retry after a release";
+    case SYEV3_E_STATE: return "invalid server handle or request state";
+    case SYEV3_E_TIMEOUT: return "timed out waiting for the request";
+    default: return "unknown error code";
+  }
+}
+
+int syev3_version(void) { return 10000; }
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+// syev3_internal.hpp -- declarations shared by the library's host sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace syev3 {
+
+constexpr int kBlock = 256;  // lanes (matrices) per workgroup: 4 wavefronts
+
+// Launch the batched solver; arguments already validated.  Returns the HIP
+// status of the launch.
+hipError_t launch_batched(int64_t n, const void* A, int64_t ld, int layout,
+                          void* lambda, void* V, int dtype, uint32_t flags,
+                          int32_t* info, hipStream_t stream);
+
+// One request of a serving tick, as the segment kernel reads it from device
+// memory.  Matrices of segment s occupy tiles [tile_begin, tile_begin +
+// ceil(n / kBlock)) of the tick's tile space, so no workgroup spans two
+// segments.
+struct Segment {
+  const void* A;
+  void* lambda;
+  void* V;        // NULL: eigenvalues only
+  int64_t n;
+  int64_t tile_begin;
+  int32_t dtype;
+  uint32_t flags;
+};
+
+// Launch the segment kernel: grid-stride over `total_tiles` tiles of the
+// table `segs` (device memory, `nseg` entries, tile_begin ascending).
+hipError_t launch_segments(const Segment* segs, int32_t nseg,
+                           int64_t total_tiles, int32_t grid_blocks,
+                           hipStream_t stream);
+
+// Device properties used for grid sizing.
+int device_cu_count();
+
+}  // namespace syev3

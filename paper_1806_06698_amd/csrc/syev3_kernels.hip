@@ -1,0 +1,184 @@
+// syev3_kernels.hip -- batched 3x3 symmetric eigensolver kernels (gfx950).
+//
+// One lane per matrix.  Each workgroup handles kBlock = 256 consecutive
+// matrices.
+//   * SoA: each of the 6 input planes and of the 3 + 9 output planes is read
+//     or written by a wavefront as one contiguous 512-byte (FP64) or 256-byte
+//     (FP32) run: fully coalesced, no LDS.
+//   * AoS: the workgroup's 256 x 6 input block is contiguous in memory; it is
+//     read with unit-stride lanes into LDS and each lane then picks up its
+//     own 6 entries (the transpose).  Outputs go back through LDS the same
+//     way, so global stores are unit-stride as well.
+// Streams are read and written once, with non-temporal hints (no reuse).
+#include <type_traits>
+
+#include "syev3_internal.hpp"
+#include "syev3_lane.hpp"
+
+namespace syev3 {
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T v, T* p) {
+  __builtin_nontemporal_store(v, p);
+}
+
+// T = double: FP64 path.  T = float: FP32 storage with FP64 refinement.
+template <typename T, bool VECS, bool INFO>
+__global__ __launch_bounds__(kBlock) void k_syev3_soa(
+    int64_t n, int64_t ld, const T* __restrict__ A, T* __restrict__ lam,
+    T* __restrict__ V, uint32_t flags, int32_t* __restrict__ info) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double a[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream(A + k * ld + i);
+  double l[3], v[9];
+  const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) st_stream((T)l[j], lam + j * ld + i);
+  if (VECS) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) st_stream((T)v[k], V + k * ld + i);
+  }
+  if (INFO) info[i] = code;
+}
+
+template <typename T, bool VECS, bool INFO>
+__global__ __launch_bounds__(kBlock) void k_syev3_aos(
+    int64_t n, const T* __restrict__ A, T* __restrict__ lam, T* __restrict__ V,
+    uint32_t flags, int32_t* __restrict__ info) {
+  __shared__ T sm[kBlock * 12];
+  const int64_t base = (int64_t)blockIdx.x * kBlock;
+  const int cnt = (int)((n - base) < kBlock ? (n - base) : kBlock);
+  const int t = threadIdx.x;
+  const T* Ab = A + base * 6;
+  for (int k = t; k < cnt * 6; k += kBlock) sm[k] = ld_stream(Ab + k);
+  __syncthreads();
+  double a[6];
+  if (t < cnt) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) a[k] = (double)sm[6 * t + k];
+  }
+  __syncthreads();
+  if (t < cnt) {
+    double l[3], v[9];
+    const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) sm[3 * t + j] = (T)l[j];
+    if (VECS) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sm[3 * kBlock + 9 * t + k] = (T)v[k];
+    }
+    if (INFO) info[base + t] = code;
+  }
+  __syncthreads();
+  for (int k = t; k < cnt * 3; k += kBlock) st_stream(sm[k], lam + base * 3 + k);
+  if (VECS) {
+    for (int k = t; k < cnt * 9; k += kBlock)
+      st_stream(sm[3 * kBlock + k], V + base * 9 + k);
+  }
+}
+
+template <typename T, bool VECS, bool INFO>
+static hipError_t launch_t(int64_t n, const void* A, int64_t ld, int layout,
+                           void* lambda, void* V, uint32_t flags, int32_t* info,
+                           hipStream_t stream) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  const dim3 grid((unsigned)blocks), block(kBlock);
+  if (layout == 0) {
+    hipLaunchKernelGGL((k_syev3_soa<T, VECS, INFO>), grid, block, 0, stream, n, ld,
+                       (const T*)A, (T*)lambda, (T*)V, flags, info);
+  } else {
+    hipLaunchKernelGGL((k_syev3_aos<T, VECS, INFO>), grid, block, 0, stream, n,
+                       (const T*)A, (T*)lambda, (T*)V, flags, info);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_dt(int64_t n, const void* A, int64_t ld, int layout,
+                            void* lambda, void* V, uint32_t flags, int32_t* info,
+                            hipStream_t stream) {
+  if (V) {
+    return info ? launch_t<T, true, true>(n, A, ld, layout, lambda, V, flags, info, stream)
+                : launch_t<T, true, false>(n, A, ld, layout, lambda, V, flags, info, stream);
+  }
+  return info ? launch_t<T, false, true>(n, A, ld, layout, lambda, V, flags, info, stream)
+              : launch_t<T, false, false>(n, A, ld, layout, lambda, V, flags, info, stream);
+}
+
+hipError_t launch_batched(int64_t n, const void* A, int64_t ld, int layout,
+                          void* lambda, void* V, int dtype, uint32_t flags,
+                          int32_t* info, hipStream_t stream) {
+  if (dtype == 0)
+    return launch_dt<double>(n, A, ld, layout, lambda, V, flags, info, stream);
+  return launch_dt<float>(n, A, ld, layout, lambda, V, flags, info, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Serving: one launch solves every request of a tick.  The grid is
+// persistent-style (sized to the device, not to the work): workgroups stride
+// over the tick's tiles; a tile is kBlock matrices of one segment, found by a
+// binary search of the (small) table, so each wavefront runs one dtype and
+// one code path.  Per-matrix arithmetic is exactly the batched kernels'.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t i) {
+  const T* A = (const T*)s.A;
+  T* lam = (T*)s.lambda;
+  T* V = (T*)s.V;
+  const int64_t ld = s.n;
+  double a[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream(A + k * ld + i);
+  double l[3], v[9];
+  if (V) {
+    solve3<true, std::is_same<T, float>::value>(a, s.flags, l, v);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) st_stream((T)v[k], V + k * ld + i);
+  } else {
+    solve3<false, std::is_same<T, float>::value>(a, s.flags, l, v);
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) st_stream((T)l[j], lam + j * ld + i);
+}
+
+__global__ __launch_bounds__(kBlock) void k_syev3_segments(
+    const Segment* __restrict__ segs, int32_t nseg, int64_t total_tiles) {
+  for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
+    // last segment whose tile_begin <= tile (uniform across the workgroup)
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (segs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    }
+    const Segment s = segs[lo];
+    const int64_t i = (tile - s.tile_begin) * kBlock + threadIdx.x;
+    if (i < s.n) {
+      if (s.dtype == 0) solve_segment_tile<double>(s, i);
+      else solve_segment_tile<float>(s, i);
+    }
+  }
+}
+
+hipError_t launch_segments(const Segment* segs, int32_t nseg,
+                           int64_t total_tiles, int32_t grid_blocks,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(k_syev3_segments, dim3((unsigned)grid_blocks), dim3(kBlock), 0,
+                     stream, segs, nseg, total_tiles);
+  return hipGetLastError();
+}
+
+int device_cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return cus > 0 ? cus : 256;
+}
+
+}  // namespace syev3

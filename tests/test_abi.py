@@ -1,0 +1,85 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/syev3.h declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1806_06698_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "syev3.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", text, flags=re.M)
+    return sorted({n for n in names if n.startswith(("batched_", "syev3_"))})
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_header_declares_the_entry_points():
+    names = _declared_functions()
+    for required in ("batched_syev3", "batched_syev3_ex", "batched_syev3_info",
+                     "syev3_strerror", "syev3_server_create", "syev3_server_submit"):
+        assert required in names
+
+
+def test_library_exports_every_declared_function(L):
+    missing = [n for n in _declared_functions() if not hasattr(L, n)]
+    assert not missing, f"declared in syev3.h but not exported: {missing}"
+
+
+def test_strerror_and_version(L):
+    for code in range(0, -12, -1):
+        s = L.syev3_strerror(code).decode()
+        assert s and s != "unknown error code"
+    assert L.syev3_version() >= 10000
+
+
+# Fake, never-dereferenced device addresses: every call below must fail in
+# argument checking, before any launch.
+A = ctypes.c_void_p(0x100000)
+LAM = ctypes.c_void_p(0x200000)
+VV = ctypes.c_void_p(0x300000)
+NUL = ctypes.c_void_p(0)
+S = ctypes.c_void_p(0)
+
+
+def test_bad_arguments_are_rejected(L):
+    ex = L.batched_syev3_ex
+    assert ex(-1, A, 0, 0, LAM, VV, 0, 0, S) == -1             # n < 0
+    assert ex(10, NUL, 0, 0, LAM, VV, 0, 0, S) == -2           # A NULL
+    assert ex(10, A, 0, 0, NUL, VV, 0, 0, S) == -2             # lambda NULL
+    assert ex(10, A, 0, 0, LAM, VV, 7, 0, S) == -3             # dtype
+    assert ex(10, A, 0, 0, LAM, VV, 1, 4, S) == -3             # Newton needs F64
+    assert ex(10, A, 0, 2, LAM, VV, 0, 0, S) == -4             # layout
+    assert ex(10, A, 5, 0, LAM, VV, 0, 0, S) == -4             # ld < n
+    assert ex(10, A, 10, 1, LAM, VV, 0, 0, S) == -4            # AoS needs ld 0
+    assert ex(10, A, 0, 0, LAM, VV, 0, 64, S) == -7            # unknown flag
+    # aliasing: lambda inside A's 6 planes; V overlapping lambda
+    assert ex(10, A, 0, 0, ctypes.c_void_p(0x100000 + 8 * 30), VV, 0, 0, S) == -5
+    assert ex(10, A, 0, 0, LAM, ctypes.c_void_p(0x200000 + 8), 0, 0, S) == -5
+    # AoS spans: A is 6n packed elements
+    assert ex(10, A, 0, 1, ctypes.c_void_p(0x100000 + 8 * 59), NUL, 0, 0, S) == -5
+    assert ex(10, A, 0, 1, ctypes.c_void_p(0x100000 + 8 * 60), NUL, 0, 0, S) != -5
+    # huge n for the grid
+    assert ex(1 << 62, A, 0, 0, LAM, VV, 0, 0, S) in (-1, -4)
+
+
+def test_n_zero_is_a_noop(L):
+    assert L.batched_syev3(0, NUL, NUL, NUL, 0, S) == 0
+    assert L.batched_syev3_ex(0, NUL, 0, 1, NUL, NUL, 1, 0, S) == 0
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+    import paper_1806_06698_amd as s3
+    with pytest.raises(ValueError):
+        s3.syev3(torch.zeros(6, 4, dtype=torch.float64))

@@ -1,0 +1,240 @@
+"""GPU path (through the C ABI) against the CPU oracle.
+
+Bar (per matrix, eigenvalues ascending on both sides):
+  |lambda_i - lambda_ref_i| <= 16 eps ||A||_F
+  ||A V - V Lambda||_F      <= 16 eps ||A||_F
+  ||V^T V - I||_F           <= 16 eps
+Eigenvectors are compared only through the two measures: their signs and the
+basis of a repeated eigenvalue are not unique.  Exact cases (diagonal input,
+beta- and combo-deflation, scaling by powers of two) are compared bitwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import checks
+import oracle
+import paper_1806_06698_amd as s3
+from gpu_common import (EPS64, device_measures, need_gpu, sample_indices,
+                        soa_to_numpy, solve_soa)
+from paper_1806_06698_amd import gen
+
+pytestmark = pytest.mark.gpu
+TOL = 16.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    oracle.build(force=False)
+
+
+def _compare_full(A_soa_cpu, flags=0, oflags=0, label=""):
+    """Solve on the GPU and with the oracle; check the bar on every matrix."""
+    A6 = gen.to_aos(A_soa_cpu).numpy()
+    lam_d, V_d = solve_soa(A_soa_cpu.cuda(), flags=flags)
+    lam, V = soa_to_numpy(lam_d, V_d)
+    lam_o, _ = oracle.solve(A6, flags=oflags)
+    eerr = checks.eig_error(A6, lam, lam_o)
+    res = checks.residual(A6, lam, V)
+    orth = checks.orthogonality(V)
+    print(f"{label} n={A6.shape[0]} max |dlam|/(eps|A|) {eerr.max():.2f} "
+          f"res {res.max():.2f} orth {orth.max():.2f}", flush=True)
+    assert np.all(np.diff(lam, axis=1) >= 0)
+    assert eerr.max() <= TOL
+    assert res.max() <= TOL
+    assert orth.max() <= TOL
+    return lam, V
+
+
+@pytest.mark.parametrize("kind,n,seed", [
+    ("normal", 4096, 0),            # the 4,096-matrix N(0,1) workload, whole
+    ("normal", 3 * 65536 + 17, 10),  # several tiles and a ragged tail
+    ("stress_mix", 200_003, 1),
+    ("spd_fe", 100_001, 2),
+    ("wide_range", 100_007, 4),
+    ("uniform", 50_000, 5),
+    ("chi2", 50_000, 6),
+])
+def test_matches_oracle_every_matrix(kind, n, seed):
+    A, _ = gen.make(kind, n, seed, "cpu")
+    _compare_full(A, label=kind)
+
+
+@pytest.mark.parametrize("flags,oflags", [
+    (s3.FLAG_SIMPLIFIED_DEFLATION, oracle.SIMPLIFIED_DEFLATION),
+    (s3.FLAG_NO_H_GUARD, oracle.NO_H_GUARD),
+    (s3.FLAG_NEWTON, oracle.NEWTON),
+])
+def test_flag_variants(flags, oflags):
+    for kind, seed in (("normal", 20), ("spd_fe", 21), ("uniform", 22)):
+        A, _ = gen.make(kind, 40_000, seed, "cpu")
+        _compare_full(A, flags=flags, oflags=oflags, label=f"{kind}/flags={flags}")
+
+
+def test_newton_on_stress_mix():
+    A, _ = gen.stress_mix(100_000, 23, "cpu")
+    _compare_full(A, flags=s3.FLAG_NEWTON, oflags=oracle.NEWTON, label="newton/stress")
+
+
+def test_layouts_and_modes_agree_bitwise():
+    A, _ = gen.stress_mix(70_001, 30, "cpu")
+    Ad = A.cuda()
+    lam_s, V_s = solve_soa(Ad)
+    lam_v, V_v = solve_soa(Ad, vectors=False)
+    assert V_v is None
+    Aa = gen.to_aos(A).cuda()
+    lam_a, V_a = s3.syev3(Aa, layout="aos")
+    lam_av, _ = s3.syev3(Aa, layout="aos", vectors=False)
+    torch.cuda.synchronize()
+    assert torch.equal(lam_s, lam_v)
+    assert torch.equal(lam_s.t(), lam_a)
+    assert torch.equal(lam_s.t(), lam_av)
+    assert torch.equal(V_s.t().reshape(-1, 3, 3), V_a)
+
+
+def test_plane_stride_larger_than_n():
+    A, _ = gen.stress_mix(50_000, 31, "cpu")
+    buf = torch.full((6, 65_536), float("nan"), dtype=torch.float64)
+    buf[:, :50_000] = A
+    lam1, V1 = solve_soa(buf.cuda()[:, :50_000])
+    lam0, V0 = solve_soa(A.cuda())
+    assert torch.equal(lam0, lam1) and torch.equal(V0, V1)
+
+
+def test_info_reports_branches_and_iterations():
+    A, cat = gen.stress_mix(100_000, 32, "cpu")
+    lam, V, info = solve_soa(A.cuda(), info=True)
+    info = info.cpu().numpy()
+    br = info & 0xFF
+    it_mu = (info >> 8) & 0xFF
+    it_nu = (info >> 16) & 0xFF
+    _, _, oinfo = oracle.solve(gen.to_aos(A).numpy(), return_info=True)
+    # branch decisions near the deflation threshold may differ (both are
+    # within the bar); they agree on nearly every matrix
+    agree = np.mean(br == oinfo[:, 0])
+    print(f"branch agreement {agree:.6f}; GPU branches {np.bincount(br, minlength=5)}; "
+          f"BG evaluations mu: mean {it_mu[br == 4].mean():.2f} max {it_mu.max()}, "
+          f"nu: mean {it_nu[br == 4].mean():.2f} max {it_nu.max()}", flush=True)
+    assert agree > 0.999
+    assert np.all(br[cat.numpy() == gen.CAT_DIAGONAL] == 2)
+    assert it_mu.max() < 32 and it_nu.max() < 32
+
+
+def test_edge_cases():
+    rows = []
+    rows.append([0.0] * 6)                                  # zero
+    rows.append([2.5, 0, 0, 2.5, 0, 2.5])                   # lambda I
+    rows.append([1e-300, 0, 0, 1e-300, 0, 1e-300])
+    rows.append([3.0, 0, 0, -1.0, 0, 2.0])                  # diagonal
+    rows.append([1.0, 0, 0, 1.0, 1e-200, 1.0])              # tiny coupling
+    rows.append([1e300, 1e299, -1e300, 2e299, 1e300, -1e300])  # huge
+    rows.append([1e-300, 2e-301, -1e-300, 3e-300, 1e-300, 0])  # tiny
+    rows.append([1.0, 1e-310, 0.5, 1.0, 0.25, 1.0])          # subnormal entry
+    rows.append([0.0, 1.0, 0.0, 0.0, 0.0, 0.0])              # only a12
+    rows.append([0.0, 0.0, 1.0, 0.0, 0.0, 0.0])              # only a13
+    rows.append([0.0, 0.0, 0.0, 0.0, 1.0, 0.0])              # only a23
+    rows.append([1.0, 1.0, 1.0, 1.0, 1.0, 1.0])              # rank one
+    A6 = np.array(rows)
+    A = torch.from_numpy(A6.T.copy())
+    lam_d, V_d = solve_soa(A.cuda())
+    lam, V = soa_to_numpy(lam_d, V_d)
+    lam_o, _ = oracle.solve(A6)
+    assert checks.eig_error(A6, lam, lam_o).max() <= TOL
+    assert checks.residual(A6, lam, V).max() <= TOL
+    assert checks.orthogonality(V).max() <= TOL
+    # zero and lambda I: exact, V = I
+    assert np.all(lam[0] == 0.0) and np.array_equal(V[0], np.eye(3))
+    assert np.all(lam[1] == 2.5) and np.array_equal(V[1], np.eye(3))
+    assert np.all(lam[2] == 1e-300)
+    assert np.array_equal(lam[3], [-1.0, 2.0, 3.0])
+
+
+def test_nonfinite_inputs_give_nan_only_there():
+    A = gen.normal(1000, 33, "cpu")
+    A[2, 5] = float("nan")
+    A[0, 17] = float("inf")
+    A[4, 999] = -float("inf")
+    lam_d, V_d = solve_soa(A.cuda())
+    lam, V = soa_to_numpy(lam_d, V_d)
+    bad = [5, 17, 999]
+    assert np.all(np.isnan(lam[bad])) and np.all(np.isnan(V[bad]))
+    good = np.setdiff1d(np.arange(1000), bad)
+    assert np.all(np.isfinite(lam[good])) and np.all(np.isfinite(V[good]))
+
+
+def test_n_zero_and_one():
+    A = torch.empty((6, 0), dtype=torch.float64, device="cuda")
+    lam, V = s3.syev3(A)
+    assert lam.shape == (3, 0)
+    A1, _ = gen.make("normal", 1, 34, "cpu")
+    _compare_full(A1, label="n=1")
+
+
+def test_exact_cases_bitwise():
+    rng = np.random.default_rng(35)
+    n = 20_000
+    # diagonal
+    D = np.zeros((n, 6))
+    D[:, [0, 3, 5]] = rng.standard_normal((n, 3))
+    lam, V = soa_to_numpy(*solve_soa(torch.from_numpy(D.T.copy()).cuda()))
+    assert np.array_equal(lam, np.sort(D[:, [0, 3, 5]], axis=1))
+    assert np.all(np.isin(V, (-1.0, 0.0, 1.0)))
+    # beta-deflation (a12 = 0, a13 = 0): a11 exactly in the spectrum
+    B = rng.standard_normal((n, 6))
+    B[:, 1] = 0.0
+    B[:, 2] = 0.0
+    lam, V = soa_to_numpy(*solve_soa(torch.from_numpy(B.T.copy()).cuda()))
+    assert np.all((lam == B[:, [0]]).any(axis=1))
+    assert checks.residual(B, lam, V).max() <= TOL
+    # combo-deflation (a12 = 0, a11 = a22)
+    C = rng.standard_normal((n, 6))
+    C[:, 1] = 0.0
+    C[:, 3] = C[:, 0]
+    lam, V = soa_to_numpy(*solve_soa(torch.from_numpy(C.T.copy()).cuda()))
+    assert np.all((lam == C[:, [0]]).any(axis=1))
+    assert checks.residual(C, lam, V).max() <= TOL
+
+
+def test_power_of_two_scaling_bitwise():
+    A, _ = gen.stress_mix(20_000, 36, "cpu")
+    keep = (A.abs().amin(0) > 1e-30).numpy()
+    A = A[:, keep].contiguous()
+    lam0, V0 = solve_soa(A.cuda())
+    for j in (-900, -1, 1, 600):
+        lam, V = solve_soa(torch.ldexp(A, torch.tensor(j)).cuda())
+        assert torch.equal(lam, torch.ldexp(lam0, torch.tensor(j, device="cuda")))
+        assert torch.equal(V, V0)
+
+
+# --------------------------------------------------------------------------
+# Full-size workloads, in the launch configuration the benchmark times:
+# every matrix checked on the device by the two measures, a sample (every
+# category represented) against the oracle.
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind,n,seed", [
+    ("stress_mix", 1 << 24, 1),
+    ("spd_fe", 1 << 26, 2),
+    ("wide_range", 1 << 28, 4),
+])
+def test_full_size(kind, n, seed):
+    print(f"full-size {kind} n={n}", flush=True)
+    A, cat = gen.make(kind, n, seed, "cuda")
+    lam, V = solve_soa(A)
+    res, orth = device_measures(A, lam, V)
+    rmax = res.max().item() / EPS64
+    omax = orth.max().item() / EPS64
+    print(f"  all {n}: max res {rmax:.2f} eps|A|, max orth {omax:.2f} eps", flush=True)
+    assert rmax <= TOL and omax <= TOL
+    idx = sample_indices(n, 20_000, seed, cat)
+    it = torch.from_numpy(idx).cuda()
+    A6 = A[:, it].t().cpu().numpy()
+    lam_s = lam[:, it].t().cpu().numpy()
+    lam_o, _ = oracle.solve(A6)
+    e = checks.eig_error(A6, lam_s, lam_o)
+    print(f"  sample {len(idx)} vs oracle: max {e.max():.2f} eps|A|", flush=True)
+    assert e.max() <= TOL
+    assert bool(torch.all(lam[1] >= lam[0]).item() and torch.all(lam[2] >= lam[1]).item())
+    del A, lam, V, res, orth
+    torch.cuda.empty_cache()
