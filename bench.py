@@ -1,0 +1,277 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched 3x3 symmetric eigensolver on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+A step is one call of the library (batched_syev3) over the whole batch: load,
+power-of-two scaling, Jacobi rotation to an ordered arrow, deflation test,
+zero finder, eigenvalues, eigenvectors, store.  Headline workload: 2^26 SPD
+3x3 matrices Q diag(e^x1, e^x2, e^x3) Q^T (x_i ~ U(0, ln 1e8), Haar Q), FP64,
+eigenvalues and eigenvectors, structure-of-arrays, inputs resident in HBM.
+Prints one JSON line.  Side measurements (FP32-storage form, other layouts,
+the stress mix, the 2^28 wide-range batch, serving) go into the same line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, vendor figure
+BYTES_PER_MATRIX = {  # algorithmic: 6 entries in, 3 (+9) out
+    ("f64", True): 144, ("f64", False): 72, ("f32r", True): 72, ("f32r", False): 36,
+}
+KERNEL_SOURCES = ["paper_1806_06698_amd/csrc/syev3_lane.hpp",
+                  "paper_1806_06698_amd/csrc/syev3_kernels.hip"]
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--headline-only", action="store_true",
+                   help="time only the headline workload (for profiler runs)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-serving", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0,
+                   help="target CPU time of the oracle baseline sample")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="run only a plain device copy of 2^30 bytes (known traffic), "
+                        "to calibrate the FETCH_SIZE/WRITE_SIZE counters")
+    return p.parse_args()
+
+
+def copy_calibration(torch):
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": src.numel() * 8, "launches": 3}))
+
+
+def timed_launches(fn, steps, warmup, torch):
+    """Run fn() warmup times, then steps times with a HIP event pair around
+    each launch on the launching (current) stream.  Returns (total_s,
+    per-launch ms list)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record()
+        fn()
+        ends[k].record()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return total, per, starts[0].elapsed_time(ends[-1]) / 1e3
+
+
+def pmc_traffic(n, khash):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None
+    when they were taken on other kernel sources or another batch size."""
+    try:
+        with open(PMC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = d.get("spd_fe_64m_f64_soa")
+    if not ent or ent.get("kernel_hash") != khash or ent.get("n") != n:
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(torch, gen, target_s):
+    """The oracle, as it is, on the host's cores: a fixed sample of the
+    headline workload's matrices, solved repeatedly until about target_s
+    seconds have passed."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.default_threads()
+    m = 1 << 22
+    A = gen.spd_fe(m, seed=2, device="cpu")
+    A6 = gen.to_aos(A).numpy()
+    oracle.solve(A6[: 1 << 16], nthreads=threads)  # warm the thread pool
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.solve(A6, nthreads=threads)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= target_s:
+            break
+    return {"value": reps * m / dt, "unit": "eigensolves/s (vals+vecs)", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{m} matrices of the SPD workload's generator (CPU draw, seed 2), "
+                      f"FP64 vals+vecs, solved {reps} times in {dt:.1f} s on {threads} "
+                      f"threads"}
+
+
+def f32r_errors(torch, gen, s3, n_sample=200_000):
+    """Per-result error of the FP32-storage form against the FP64 oracle on
+    a sample of the SPD workload (the FP32 inputs, exactly widened)."""
+    import numpy as np
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import checks
+    A = gen.spd_fe(n_sample, seed=2, device="cuda").float()
+    lam, V = s3.syev3(A)
+    torch.cuda.synchronize()
+    A6 = A.t().double().cpu().numpy()
+    lam_o, _ = oracle.solve(A6)
+    l = lam.t().double().cpu().numpy()
+    Vn = V.t().double().cpu().numpy().reshape(-1, 3, 3)
+    rel = np.abs(l - lam_o) / np.abs(lam_o)
+    res = checks.residual(A6, l, Vn) * checks.EPS64 / checks.EPS32
+    orth = checks.orthogonality(Vn) * checks.EPS64 / checks.EPS32
+    q = lambda x: [float(np.median(x)), float(np.percentile(x, 99)), float(x.max())]
+    return {"sample": n_sample,
+            "rel_err_lambda_[min,mid,max]_median_p99_max": [q(rel[:, j]) for j in range(3)],
+            "residual_eps32_median_p99_max": q(res),
+            "orth_eps32_median_p99_max": q(orth),
+            "oracle_floor_note": "FP64 oracle absolute error ~eps64*1e8 relative to "
+                                 "lambda_min on cond<=1e8: relative errors below ~2e-8 "
+                                 "on lambda_min are not resolvable"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; "
+                          "--gpus must be 1 (the batch shards trivially across GPUs, "
+                          "see the design notes)"}))
+        sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+    import paper_1806_06698_amd as s3
+    from paper_1806_06698_amd import gen
+
+    dev = "cuda"
+    n = 1 << 26
+    khash = kernel_hash()
+    A = gen.spd_fe(n, seed=2, device=dev)
+    lam = torch.empty((3, n), dtype=torch.float64, device=dev)
+    V = torch.empty((9, n), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        s3.syev3(A, out=(lam, V))
+
+    total_s, per_ms, span_s = timed_launches(step, args.steps, args.warmup, torch)
+    ms_launch = sum(per_ms) / len(per_ms)
+    ms_per_step = span_s * 1e3 / args.steps
+    value = n * args.steps / span_s
+    bytes_launch = BYTES_PER_MATRIX[("f64", True)] * n
+    achieved = bytes_launch / (ms_launch * 1e-3) / 1e9
+    traffic = pmc_traffic(n, khash)
+    line = {
+        "metric": "3x3 eigensolves/sec (vals+vecs) & HBM GB/s vs peak; served p50/p99 latency",
+        "value": value,
+        "unit": "eigensolves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "spd_fe_64m: 2^26 SPD 3x3 Q diag(e^x) Q^T, x~U(0, ln 1e8), "
+                               "FP64 eigenvalues+eigenvectors, SoA, ld=n",
+                   "n": n, "layout": "soa", "vectors": True, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "k_syev3_soa<double, vecs>",
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "ms_per_launch": ms_launch},
+        "kernel_hash": khash,
+    }
+    del A, lam, V
+    torch.cuda.empty_cache()
+
+    if not args.headline_only:
+        side = {}
+
+        def run_variant(name, A, layout, vectors, dtype_key, steps=10):
+            nn = A.shape[1] if layout == "soa" else A.shape[0]
+            out = s3.syev3(A, layout=layout, vectors=vectors)
+            torch.cuda.synchronize()
+            fn = (lambda: s3.syev3(A, layout=layout, vectors=vectors, out=out))
+            _, per, span = timed_launches(fn, steps, 2, torch)
+            msl = sum(per) / len(per)
+            b = BYTES_PER_MATRIX[(dtype_key, vectors)] * nn
+            side[name] = {"n": nn, "ms_per_launch": msl, "eigensolves_per_s": nn / (msl * 1e-3),
+                          "algorithmic_GBps": b / (msl * 1e-3) / 1e9,
+                          "hbm_frac": b / (msl * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            del out
+
+        A = gen.spd_fe(n, seed=2, device=dev)
+        Af = A.float()
+        run_variant("spd_fe_64m_f32r_soa", Af, "soa", True, "f32r")
+        run_variant("spd_fe_64m_f64_soa_valsonly", A, "soa", False, "f64")
+        Aa = A.t().contiguous()
+        run_variant("spd_fe_64m_f64_aos", Aa, "aos", True, "f64")
+        del Aa, Af
+        side["f32r_speedup_vs_f64"] = (line["roofline"]["ms_per_launch"]
+                                       / side["spd_fe_64m_f32r_soa"]["ms_per_launch"])
+        del A
+        torch.cuda.empty_cache()
+        A, _ = gen.stress_mix(1 << 24, seed=1, device=dev)
+        run_variant("stress_mix_16m_f64_soa", A, "soa", True, "f64")
+        del A
+        torch.cuda.empty_cache()
+        A, _ = gen.wide_range(1 << 28, seed=4, device=dev)
+        run_variant("wide_range_256m_f64_soa", A, "soa", True, "f64", steps=5)
+        run_variant("wide_range_256m_f64_soa_valsonly", A, "soa", False, "f64", steps=5)
+        del A
+        torch.cuda.empty_cache()
+        A, _ = gen.wide_range(1 << 28, seed=4, device=dev)
+        Aa = A.t().contiguous()
+        del A
+        torch.cuda.empty_cache()
+        run_variant("wide_range_256m_f64_aos", Aa, "aos", True, "f64", steps=5)
+        del Aa
+        torch.cuda.empty_cache()
+        line["variants"] = side
+        try:
+            line["f32r_error_vs_fp64_oracle"] = f32r_errors(torch, gen, s3)
+        except Exception as exc:  # report, do not hide the headline
+            line["f32r_error_vs_fp64_oracle"] = {"error": repr(exc)}
+        if not args.no_serving:
+            try:
+                from paper_1806_06698_amd import serve
+                line["serving"] = serve.bench(duration_s=4.0)
+            except Exception as exc:
+                line["serving"] = {"error": repr(exc)}
+
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(torch, gen, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

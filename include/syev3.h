@@ -172,8 +172,9 @@ typedef struct {
   int64_t submitted, completed, ticks;
   int64_t matrices_completed;
   uint64_t pool_bytes_in_use, pool_bytes_peak;
-  int32_t requests_waiting_admission_peak;
+  int64_t acquire_rejections;  /* acquire calls answered SYEV3_E_AGAIN */
   int32_t inflight_ticks_peak;
+  int32_t segments_per_tick_peak;
   double busy_seconds;         /* wall time with at least one tick on the GPU */
 } syev3_server_stats;
 
@@ -194,8 +195,10 @@ int syev3_server_destroy(syev3_server* s);
 int64_t syev3_server_acquire(syev3_server* s, int64_t n, int dtype,
                              int want_vectors, syev3_request_buffers* bufs);
 
-/* Queue an admitted request for the next tick.  Its A must be complete. */
-int syev3_server_submit(syev3_server* s, int64_t request);
+/* Queue an admitted request for the next tick.  Its A must be complete
+ * when `ready` (a hipEvent_t, or NULL) has completed: the tick waits for it
+ * on the device, the host does not block. */
+int syev3_server_submit(syev3_server* s, int64_t request, hipEvent_t ready);
 
 /* 1 if the request's results are complete, 0 if not yet, < 0 on error.
  * If done and latency_s is not NULL, it receives submit-to-completion time
@@ -210,6 +213,47 @@ int syev3_server_wait(syev3_server* s, int64_t request, double timeout_s,
 int syev3_server_release(syev3_server* s, int64_t request);
 
 int syev3_server_get_stats(syev3_server* s, syev3_server_stats* out);
+
+/*
+ * Load generator for a server (benchmark support).  Open loop (qps > 0):
+ * requests arrive as a Poisson process of rate qps for duration_s seconds.
+ * Closed loop (qps == 0): closed_concurrency requests are kept in flight, a
+ * new one arriving when one completes, for duration_s seconds.  Each has
+ * n = floor(2^U(0, max_log2_n)) matrices (at most src_n) and is FP32-storage
+ * with probability frac_f32, else FP64.  Its input is copied on the device
+ * from a source pool (SoA, ld = src_n, one pool per dtype) at a random
+ * offset, then submitted; a request that does not fit waits (FIFO) until
+ * releases make room.  Completed requests are released at once.  Latency is
+ * measured from arrival (so it includes waiting for admission) to the
+ * scheduler's observation of the tick's completion event.
+ */
+typedef struct {
+  double qps;            /* > 0: open loop (Poisson); 0: closed loop */
+  int32_t closed_concurrency; /* closed loop: requests kept in flight */
+  double duration_s;
+  double max_log2_n;
+  double frac_f32;
+  uint64_t seed;
+  const void* src_f64;   /* device, 6 planes of src_n doubles */
+  const void* src_f32;   /* device, 6 planes of src_n floats */
+  int64_t src_n;
+  int32_t want_vectors;
+} syev3_loadgen_opts;
+
+typedef struct {
+  int64_t requests, matrices;
+  double elapsed_s;              /* first arrival to last completion */
+  double matrices_per_s, requests_per_s;
+  double lat_p50_s, lat_p90_s, lat_p99_s, lat_p999_s, lat_max_s, lat_mean_s;
+  double admit_wait_mean_s;      /* arrival to admission */
+  int64_t ticks;
+  double mean_segments_per_tick;
+  int32_t inflight_ticks_peak;
+  uint64_t pool_bytes_peak;
+} syev3_loadgen_result;
+
+int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* opts,
+                         syev3_loadgen_result* out);
 
 #ifdef __cplusplus
 }

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace syev3 {
@@ -28,10 +29,23 @@ struct Segment {
   uint32_t flags;
 };
 
-// Launch the segment kernel: grid-stride over `total_tiles` tiles of the
-// table `segs` (device memory, `nseg` entries, tile_begin ascending).
-hipError_t launch_segments(const Segment* segs, int32_t nseg,
-                           int64_t total_tiles, int32_t grid_blocks,
+// A tick's table in device memory: header, then the segments in ascending
+// tile_begin order.  Sized for kMaxSegmentsPerTick; only nseg are read.
+constexpr int kMaxSegmentsPerTick = 1024;
+struct TickTable {
+  int32_t nseg;
+  int32_t reserved;
+  int64_t total_tiles;
+  Segment seg[kMaxSegmentsPerTick];
+};
+// Bytes of a table with room for `max_segments` segments.
+inline size_t tick_table_bytes(int max_segments) {
+  return offsetof(TickTable, seg) + sizeof(Segment) * (size_t)max_segments;
+}
+
+// Launch the segment kernel on a table in device memory: grid_blocks
+// workgroups stride over the table's tiles.
+hipError_t launch_segments(const TickTable* table, int32_t grid_blocks,
                            hipStream_t stream);
 
 // Device properties used for grid sizing.

@@ -147,16 +147,17 @@ __device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t i) 
   for (int j = 0; j < 3; ++j) st_stream((T)l[j], lam + j * ld + i);
 }
 
-__global__ __launch_bounds__(kBlock) void k_syev3_segments(
-    const Segment* __restrict__ segs, int32_t nseg, int64_t total_tiles) {
+__global__ __launch_bounds__(kBlock) void k_syev3_segments(const TickTable* __restrict__ t) {
+  const int nseg = t->nseg;
+  const int64_t total_tiles = t->total_tiles;
   for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
     // last segment whose tile_begin <= tile (uniform across the workgroup)
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (segs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+      if (t->seg[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
     }
-    const Segment s = segs[lo];
+    const Segment s = t->seg[lo];
     const int64_t i = (tile - s.tile_begin) * kBlock + threadIdx.x;
     if (i < s.n) {
       if (s.dtype == 0) solve_segment_tile<double>(s, i);
@@ -165,11 +166,10 @@ __global__ __launch_bounds__(kBlock) void k_syev3_segments(
   }
 }
 
-hipError_t launch_segments(const Segment* segs, int32_t nseg,
-                           int64_t total_tiles, int32_t grid_blocks,
+hipError_t launch_segments(const TickTable* table, int32_t grid_blocks,
                            hipStream_t stream) {
   hipLaunchKernelGGL(k_syev3_segments, dim3((unsigned)grid_blocks), dim3(kBlock), 0,
-                     stream, segs, nseg, total_tiles);
+                     stream, table);
   return hipGetLastError();
 }
 

@@ -52,13 +52,59 @@ enum Branch : int { kZero = 0, kNonFinite = 1, kDiagonal = 2, kDeflated = 3,
                     kReduced = 4 };
 
 // ---------------------------------------------------------------------------
-// Arithmetic primitives.
+// Arithmetic primitives.  gfx950's v_rcp_f64, v_rsq_f64 and v_sqrt_f64 are
+// accurate to about 2^-24 (measured); Newton-Raphson / Goldschmidt steps
+// built from FMAs bring them to the rounding level at a fraction of the cost
+// of the IEEE-exact division and square-root sequences.  Arguments must be
+// normal positive numbers (or, for rcp, any normal non-zero number).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
-__device__ __forceinline__ double dsqrt(double x) { return __builtin_sqrt(x); }
-__device__ __forceinline__ double drcp(double x) { return 1.0 / x; }
-__device__ __forceinline__ double drsqrt(double x) { return 1.0 / __builtin_sqrt(x); }
-__device__ __forceinline__ double ddiv(double a, double b) { return a / b; }
+
+// 1/x to ~2^-48 (one Newton-Raphson step).
+__device__ __forceinline__ double rcp1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
+// a/b to about one ulp from a ~2^-47 reciprocal rb of b: quotient plus one
+// residual correction.
+__device__ __forceinline__ double div_r(double a, double b, double rb) {
+  const double q = a * rb;
+  return __builtin_fma(__builtin_fma(-b, q, a), rb, q);
+}
+
+__device__ __forceinline__ double ddiv(double a, double b) { return div_r(a, b, rcp1(b)); }
+
+// 1/sqrt(x) to about one ulp: v_rsq_f64 and two Goldschmidt steps
+// (g -> sqrt(x), h -> 1/(2 sqrt(x))).
+__device__ __forceinline__ double rsqrt2(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  r = __builtin_fma(-g, h, 0.5);
+  h = __builtin_fma(h, r, h);
+  return 2.0 * h;
+}
+
+// sqrt(x) to ~2^-47 for x >= 0: one Goldschmidt step (0 maps to 0).
+__device__ __forceinline__ double sqrt1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double g = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-g, h, 0.5);
+  return x > 0.0 ? __builtin_fma(g, r, g) : 0.0;
+}
+
+// sqrt(x) to about one ulp: one Goldschmidt step and a residual correction.
+__device__ __forceinline__ double sqrt2(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  return __builtin_fma(__builtin_fma(-g, g, x), h, g);
+}
 
 // ---------------------------------------------------------------------------
 // 2x2 symmetric eigenproblem [[p, r], [r, q]] by one Jacobi rotation.
@@ -76,10 +122,10 @@ __device__ __forceinline__ Rot2 rot2(double p, double r, double q) {
   const double ad = dabs(d);
   double t = 0.0;
   if (__builtin_fmax(ad, dabs(r)) >= 0x1p-500) {
-    const double rr = dsqrt(__builtin_fma(d, d, r * r));
+    const double rr = sqrt2(__builtin_fma(d, d, r * r));
     t = ddiv(d >= 0.0 ? r : -r, ad + rr);
   }
-  const double c = drsqrt(__builtin_fma(t, t, 1.0));
+  const double c = rsqrt2(__builtin_fma(t, t, 1.0));
   const double s = t * c;
   const double a1 = __builtin_fma(-t, r, p);
   const double a2 = __builtin_fma(t, r, q);
@@ -96,60 +142,87 @@ __device__ __forceinline__ Rot2 rot2(double p, double r, double q) {
 
 // ---------------------------------------------------------------------------
 // Fully reduced arrow [[0, 0, b1], [0, -ab, b2], [b1, b2, gb]] (Sec. 1.4):
-// spectral function f(x) = x - gb - b1^2/x - b2^2/(x + ab), rightmost zero.
-// The arguments carry b1^2 and b2^2.
+// spectral function f(x) = x - gb - b1^2/x - b2^2/(x + ab), its rightmost
+// zero.  The structure carries b1^2 and b2^2.
 // ---------------------------------------------------------------------------
 struct Arrow1 {
   double b1s, b2s, ab, gb;
 };
+
+// f and f' at x > 0, with b1^2/x and b2^2/(x + ab) to about one ulp from a
+// single reciprocal of x (x + ab).
+struct Spec {
+  double f, fp, rx, rp, q2;
+};
+
+__device__ __forceinline__ Spec spec_eval(const Arrow1& P, double x) {
+  const double p = x + P.ab;
+  const double r = rcp1(x * p);
+  const double rx = p * r, rp = x * r;
+  const double q1 = div_r(P.b1s, x, rx);
+  const double q2 = div_r(P.b2s, p, rp);
+  Spec s;
+  s.f = ((x - P.gb) - q1) - q2;
+  s.fp = __builtin_fma(q1, rx, __builtin_fma(q2, rp, 1.0));
+  s.rx = rx;
+  s.rp = rp;
+  s.q2 = q2;
+  return s;
+}
 
 // x0: positive zero of x - gb - (b1^2 + b2^2)/x (the model from +infinity),
 // in the conjugate form when gb < 0.
 __device__ __forceinline__ double bg_start(const Arrow1& P) {
   const double H = P.b1s + P.b2s;
   const double g2 = 0.5 * P.gb;
-  const double disc = dsqrt(__builtin_fma(g2, g2, H));
+  const double disc = sqrt2(__builtin_fma(g2, g2, H));
   return P.gb >= 0.0 ? g2 + disc : ddiv(H, disc - g2);
 }
 
-// One Borges-Gragg step at x.  Sets stop (and returns x) when the stop test
-// f/f' <= 2 eps x holds at x, when rounding has reached the root (f <= 0),
-// or when the step no longer decreases x.
+// One Borges-Gragg step from x (to the right of the zero).  Sets stop when
+// the returned value is final:
+//   * f(x) <= 0: x is at or just left of the zero (rounding); returns x
+//     after one Newton step, which from the left converges monotonically
+//     (Sec. 1.4.2);
+//   * the step does not decrease x; returns x;
+//   * f/f' - (x - x_new) <= 2 eps x_new: by the mean-value bound of the
+//     paper's stop test, x - zero < f/f', so x_new - zero < f/f' - (x -
+//     x_new), and x_new is the zero to relative precision 2 eps; returns
+//     x_new.  (The paper's test f/f' < 2 eps x is the special case of a
+//     vanishing step.)
 __device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop) {
-  const double p = x + P.ab;
-  const double rx = drcp(x);
-  const double rp = drcp(p);
-  const double q1 = P.b1s * rx;
-  const double q2 = P.b2s * rp;
-  const double f = ((x - P.gb) - q1) - q2;
-  const double fp = __builtin_fma(q1, rx, __builtin_fma(q2, rp, 1.0));
-  if (f <= 0.0 || f <= 2.0 * kEps64 * x * fp) {
+  const Spec s = spec_eval(P, x);
+  if (s.f <= 0.0) {
     stop = true;
-    return x;
+    return x - ddiv(s.f, s.fp);
   }
-  // model: w0 = 1 + b2^2 ab / p^3; a = -w0/x; b = f' + f/x
-  const double w0 = __builtin_fma(q2 * P.ab, rp * rp, 1.0);
-  const double a = -w0 * rx;
-  const double b = __builtin_fma(f, rx, fp);
-  // increment: a D^2 + b D - f = 0, D = (2f/b) / (1 + sqrt(1 + (2a/b)(2f/b)))
-  const double F = ddiv(2.0 * f, b);
-  const double D = __builtin_fmax(0.0, __builtin_fma(ddiv(2.0 * a, b), F, 1.0));
-  const double dl = ddiv(F, 1.0 + dsqrt(D));
+  // model phi = w0 x - sigma - w1/x matching f, f', f'' at x:
+  // w0 = 1 + b2^2 ab / p^3; the increment D solves a D^2 + b D - f = 0 with
+  // a = -w0/x and b = f' + f/x; D = 2f / (b + sqrt(b^2 + 4 a f)).
+  const double w0 = __builtin_fma(s.q2 * P.ab, s.rp * s.rp, 1.0);
+  const double a = -w0 * s.rx;
+  const double b = __builtin_fma(s.f, s.rx, s.fp);
+  const double disc = __builtin_fmax(0.0, __builtin_fma(b, b, 4.0 * a * s.f));
+  // D to ~2^-46: an overshoot of the zero by the error of D, which cubic
+  // convergence can leave within reach, must stay below the rounding level
+  const double dl = (2.0 * s.f) * rcp1(b + sqrt1(disc));
   double xn;
   if (dl <= 0.5 * x) {
     xn = x - dl;
   } else {
-    // zero of w0 x^2 - sigma x - w1 = 0 without cancellation
-    const double r = x * rp;
+    // The step removes more than half of x: take x_new as the zero of
+    // w0 x^2 - sigma x - w1 = 0 directly (no cancellation next to the pole).
+    const double r = x * s.rp;
     const double w1 = __builtin_fma(P.b2s * r, r * r, P.b1s);
-    const double sigma = (w0 * x - w1 * rx) - f;
-    const double disc = dsqrt(__builtin_fma(sigma, sigma, 4.0 * w0 * w1));
-    xn = sigma >= 0.0 ? ddiv(sigma + disc, 2.0 * w0) : ddiv(2.0 * w1, disc - sigma);
+    const double sigma = (w0 * x - w1 * s.rx) - s.f;
+    const double sq = sqrt2(__builtin_fma(sigma, sigma, 4.0 * w0 * w1));
+    xn = sigma >= 0.0 ? ddiv(sigma + sq, 2.0 * w0) : ddiv(2.0 * w1, sq - sigma);
   }
   if (!(xn < x)) {
     stop = true;
     return x;
   }
+  if (__builtin_fma(-(x - xn), s.fp, s.f) <= 2.0 * kEps64 * xn * s.fp) stop = true;
   return xn;
 }
 
@@ -157,23 +230,17 @@ __device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop)
 // i.e. x0 = gb/2 + sqrt((gb/2)^2 + b1^2); stop when |f| < 2 eps x.
 __device__ __forceinline__ double newton_start(const Arrow1& P) {
   const double g2 = 0.5 * P.gb;
-  const double disc = dsqrt(__builtin_fma(g2, g2, P.b1s));
+  const double disc = sqrt2(__builtin_fma(g2, g2, P.b1s));
   return P.gb >= 0.0 ? g2 + disc : ddiv(P.b1s, disc - g2);
 }
 
 __device__ __forceinline__ double newton_step(const Arrow1& P, double x, bool& stop) {
-  const double p = x + P.ab;
-  const double rx = drcp(x);
-  const double rp = drcp(p);
-  const double q1 = P.b1s * rx;
-  const double q2 = P.b2s * rp;
-  const double f = ((x - P.gb) - q1) - q2;
-  if (f >= 0.0 || -f < 2.0 * kEps64 * x) {
+  const Spec s = spec_eval(P, x);
+  if (s.f >= 0.0 || -s.f < 2.0 * kEps64 * x) {
     stop = true;
     return x;
   }
-  const double fp = __builtin_fma(q1, rx, __builtin_fma(q2, rp, 1.0));
-  const double xn = x - ddiv(f, fp);
+  const double xn = x - ddiv(s.f, s.fp);
   if (!(xn > x)) {
     stop = true;
     return x;
@@ -213,7 +280,8 @@ __device__ __forceinline__ void zeros_newton(const Arrow1& P1, const Arrow1& P2,
 
 // ---------------------------------------------------------------------------
 // FP32 Borges-Gragg for the FP32-storage form: the same iteration in single
-// precision, stop when f/f' <= 2 eps32 x.
+// precision (v_rcp_f32 and v_sqrt_f32 are accurate to about one ulp).
+// conv reports a stop by the precision test or at the zero.
 // ---------------------------------------------------------------------------
 struct Arrow1f {
   float b1s, b2s, ab, gb;
@@ -222,19 +290,19 @@ struct Arrow1f {
 __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
   const float H = P.b1s + P.b2s;
   const float g2 = 0.5f * P.gb;
-  const float disc = __builtin_sqrtf(__builtin_fmaf(g2, g2, H));
-  return P.gb >= 0.0f ? g2 + disc : H / (disc - g2);
+  const float disc = __builtin_amdgcn_sqrtf(__builtin_fmaf(g2, g2, H));
+  return P.gb >= 0.0f ? g2 + disc : H * __builtin_amdgcn_rcpf(disc - g2);
 }
 
 __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop, bool& conv) {
   const float p = x + P.ab;
-  const float rx = 1.0f / x;
-  const float rp = 1.0f / p;
+  const float rx = __builtin_amdgcn_rcpf(x);
+  const float rp = __builtin_amdgcn_rcpf(p);
   const float q1 = P.b1s * rx;
   const float q2 = P.b2s * rp;
   const float f = ((x - P.gb) - q1) - q2;
   const float fp = __builtin_fmaf(q1, rx, __builtin_fmaf(q2, rp, 1.0f));
-  if (f <= 0.0f || f <= 2.0f * kEps32 * x * fp) {
+  if (f <= 0.0f) {
     stop = true;
     conv = true;
     return x;
@@ -242,9 +310,8 @@ __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop
   const float w0 = __builtin_fmaf(q2 * P.ab, rp * rp, 1.0f);
   const float a = -w0 * rx;
   const float b = __builtin_fmaf(f, rx, fp);
-  const float F = 2.0f * f / b;
-  const float D = __builtin_fmaxf(0.0f, __builtin_fmaf(2.0f * a / b, F, 1.0f));
-  const float dl = F / (1.0f + __builtin_sqrtf(D));
+  const float disc = __builtin_fmaxf(0.0f, __builtin_fmaf(b, b, 4.0f * a * f));
+  const float dl = (2.0f * f) * __builtin_amdgcn_rcpf(b + __builtin_amdgcn_sqrtf(disc));
   float xn;
   if (dl <= 0.5f * x) {
     xn = x - dl;
@@ -252,52 +319,50 @@ __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop
     const float r = x * rp;
     const float w1 = __builtin_fmaf(P.b2s * r, r * r, P.b1s);
     const float sigma = (w0 * x - w1 * rx) - f;
-    const float disc = __builtin_sqrtf(__builtin_fmaf(sigma, sigma, 4.0f * w0 * w1));
-    xn = sigma >= 0.0f ? (sigma + disc) / (2.0f * w0) : 2.0f * w1 / (disc - sigma);
+    const float sq = __builtin_amdgcn_sqrtf(__builtin_fmaf(sigma, sigma, 4.0f * w0 * w1));
+    xn = sigma >= 0.0f ? (sigma + sq) * __builtin_amdgcn_rcpf(2.0f * w0)
+                       : (2.0f * w1) * __builtin_amdgcn_rcpf(sq - sigma);
   }
   if (!(xn < x)) {
     stop = true;
     conv = true;
     return x;
   }
+  if (__builtin_fmaf(-(x - xn), fp, f) <= 4.0f * kEps32 * xn * fp) {
+    stop = true;
+    conv = true;
+  }
   return xn;
 }
 
-// One FP64 Newton step on f from an FP32 zero (Sec. 1.4.2's iteration,
-// applied once as a refinement).  Returns the refined zero; sets bad when
-// the correction is not small (the FP32 zero was not close).
+// One FP64 Newton step on f from an FP32 zero (the iteration of Sec. 1.4.2
+// applied once, as a refinement).  bad reports a correction that is not
+// small (the FP32 zero was not close).
 __device__ __forceinline__ double newton_refine(const Arrow1& P, double x, bool& bad) {
-  const double p = x + P.ab;
-  const double rx = drcp(x);
-  const double rp = drcp(p);
-  const double q1 = P.b1s * rx;
-  const double q2 = P.b2s * rp;
-  const double f = ((x - P.gb) - q1) - q2;
-  const double fp = __builtin_fma(q1, rx, __builtin_fma(q2, rp, 1.0));
-  const double dx = ddiv(f, fp);
+  const Spec s = spec_eval(P, x);
+  const double dx = ddiv(s.f, s.fp);
   const double xn = x - dx;
   bad = !(dabs(dx) <= 0x1p-12 * x) || !(xn > 0.0);
   return xn;
 }
 
 // ---------------------------------------------------------------------------
-// The whole solve.  Input: the 6 unique entries (any finite doubles, or
-// not).  Output: lam ascending, V[3r + c] = row r of eigenvector c.
-// MODE_F32R selects the FP32 zero finder with FP64 refinement and an FP64
-// re-orthogonalisation of the eigenvectors.
+// The whole solve.  Input: the 6 unique entries (any doubles).  Output: lam
+// ascending, V[3r + c] = row r of eigenvector c.  F32R selects the FP32 zero
+// finder with FP64 refinement and an FP64 re-orthogonalisation.
 // Returns branch | it_mu << 8 | it_nu << 16.
 // ---------------------------------------------------------------------------
 struct Vec3 {
   double x, y, z;
 };
 
-__device__ __forceinline__ Vec3 normalized(Vec3 u) {
-  const double r = drsqrt(__builtin_fma(u.x, u.x, __builtin_fma(u.y, u.y, u.z * u.z)));
-  return Vec3{u.x * r, u.y * r, u.z * r};
-}
-
 __device__ __forceinline__ double dot(const Vec3& a, const Vec3& b) {
   return __builtin_fma(a.x, b.x, __builtin_fma(a.y, b.y, a.z * b.z));
+}
+
+__device__ __forceinline__ Vec3 normalized(Vec3 u) {
+  const double r = rsqrt2(dot(u, u));
+  return Vec3{u.x * r, u.y * r, u.z * r};
 }
 
 __device__ __forceinline__ Vec3 axpy(double s, const Vec3& a, const Vec3& b) {
@@ -333,12 +398,13 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
   const double be2 = __builtin_fma(J.k12, a13, J.k22 * a23);
   const double ga = a33;
 
-  // Sec. 1.1: h, Givens rotation, deflation test
-  const double h = dsqrt(__builtin_fma(be1, be1, be2 * be2));
-  const bool diag = (flags & kFlagNoHGuard)
-                        ? (h == 0.0)
-                        : (h <= kEps64 * (dabs(al1) + dabs(al2) + dabs(ga)));
-  const double rh = drcp(h);
+  // Sec. 1.1: h = ||beta||, the Givens rotation G and the deflation test.
+  // h <= eps (|alpha1| + |alpha2| + |gamma|) is tested as h^2 <= (eps ...)^2.
+  const double hh = __builtin_fma(be1, be1, be2 * be2);
+  const double tol_h = kEps64 * (dabs(al1) + dabs(al2) + dabs(ga));
+  const bool diag = (flags & kFlagNoHGuard) ? (hh == 0.0) : !(hh > tol_h * tol_h);
+  const double rh = rsqrt2(hh);  // unused (inf/NaN) on diagonal lanes
+  const double h = hh * rh;
   const double cg = be2 * rh;  // G = [[cg, -sg, 0], [sg, cg, 0], [0, 0, 1]]
   const double sg = be1 * rh;
   const double al = al1 - al2;
@@ -350,25 +416,49 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
   const double rhs = (flags & kFlagSimplified) ? dabs(al1 + al2) : dabs(d1) + dabs(d2);
   const bool defl = !diag && dabs(ee) <= kEps64 * rhs;
 
-  // Three eigenpairs, two of them known to be ordered: (lx, ux) >= (ly, uy);
-  // (lz, uz) anywhere.  Vectors in arrow coordinates.
-  // Diagonal arrow: (alpha1, e1), (alpha2, e2), (gamma, e3).
-  double lx = al1, ly = al2, lz = ga;
-  Vec3 ux{1.0, 0.0, 0.0}, uy{0.0, 1.0, 0.0}, uz{0.0, 0.0, 1.0};
-  int branch = diag ? kDiagonal : kDeflated;
-  int it1 = 0, it2 = 0;
-  if (defl) {
-    // accept d1 with G^T e1 = (cg, -sg, 0); solve [[d2, h], [h, gamma]]
-    const Rot2 T = rot2(d2, h, ga);
-    lx = T.l1;
-    ly = T.l2;
-    lz = d1;
-    if (VECS) {
+  double l0, l1, l2;  // ascending
+  Vec3 v0, v1, v2;    // their eigenvectors, arrow coordinates
+  int branch, it1 = 0, it2 = 0;
+  if (diag || defl) {
+    // Two pairs known ordered, (lx, ux) >= (ly, uy); (lz, uz) anywhere.
+    double lx, ly, lz;
+    Vec3 ux, uy, uz;
+    if (defl) {
+      // accept d1 with G^T e1 = (cg, -sg, 0); solve [[d2, h], [h, gamma]]
+      branch = kDeflated;
+      const Rot2 T = rot2(d2, h, ga);
+      lx = T.l1;
+      ly = T.l2;
+      lz = d1;
       ux = Vec3{sg * T.k11, cg * T.k11, T.k21};  // G^T (0, p, q)
       uy = Vec3{sg * T.k12, cg * T.k12, T.k22};
       uz = Vec3{cg, -sg, 0.0};
+    } else {
+      // diagonal arrow: (alpha1, e1), (alpha2, e2), (gamma, e3)
+      branch = kDiagonal;
+      lx = al1;
+      ly = al2;
+      lz = ga;
+      ux = Vec3{1.0, 0.0, 0.0};
+      uy = Vec3{0.0, 1.0, 0.0};
+      uz = Vec3{0.0, 0.0, 1.0};
     }
-  } else if (!diag) {
+    // Ascending, stable in the listing order x, y, z for ties: when
+    // lx == ly the two trade vectors first, so equal eigenvalues keep their
+    // arrow order (lambda I and 0 give V = I).
+    if (lx == ly) {
+      const Vec3 tu = ux;
+      ux = uy;
+      uy = tu;
+    }
+    if (lz < ly) {
+      l0 = lz; l1 = ly; l2 = lx; v0 = uz; v1 = uy; v2 = ux;
+    } else if (lz < lx) {
+      l0 = ly; l1 = lz; l2 = lx; v0 = uy; v1 = uz; v2 = ux;
+    } else {
+      l0 = ly; l1 = lx; l2 = lz; v0 = uy; v1 = ux; v2 = uz;
+    }
+  } else {
     branch = kReduced;
     // mu: rightmost zero of A - alpha1 I; nu: of P(alpha2 I - A)P
     const double b1s = be1 * be1, b2s = be2 * be2;
@@ -405,46 +495,27 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
     } else {
       zeros_bg(P1, P2, mu, nu, it1, it2);
     }
-    lx = al1 + mu;                                   // lambda1
-    ly = al2 - nu;                                   // lambda3
-    lz = __builtin_fmin(__builtin_fmax((ga - mu) + nu, ly), lx);  // lambda2
+    // lambda3 <= lambda2 <= lambda1; lambda2 by the trace identity
+    l2 = al1 + mu;
+    l0 = al2 - nu;
+    l1 = __builtin_fmin(__builtin_fmax((ga - mu) + nu, l0), l2);
     if (VECS) {
       const double mua = mu + al, nua = nu + al;
-      Vec3 u1{be1 * mua, be2 * mu, mu * mua};
-      Vec3 u3{be1 * nu, be2 * nua, -nu * nua};
-      Vec3 u2{-be2 * mu * nua, be1 * nu * mua, be1 * be2 * al};
-      u1 = normalized(u1);
-      u3 = normalized(u3);
-      u2 = normalized(u2);
+      const Vec3 u1{be1 * mua, be2 * mu, mu * mua};
+      const Vec3 u3{be1 * nu, be2 * nua, -nu * nua};
+      const Vec3 u2{-be2 * mu * nua, be1 * nu * mua, be1 * be2 * al};
+      v2 = normalized(u1);
+      v0 = normalized(u3);
+      v1 = normalized(u2);
       if (F32R) {
         // one modified Gram-Schmidt pass over (u1, u3, u2)
-        u3 = normalized(axpy(-dot(u1, u3), u1, u3));
-        u2 = axpy(-dot(u1, u2), u1, u2);
-        u2 = normalized(axpy(-dot(u3, u2), u3, u2));
+        v0 = normalized(axpy(-dot(v2, v0), v2, v0));
+        v1 = axpy(-dot(v2, v1), v2, v1);
+        v1 = normalized(axpy(-dot(v0, v1), v0, v1));
       }
-      ux = u1;
-      uy = u3;
-      uz = u2;
     }
   }
 
-  // Ascending order of (lx >= ly, lz), stable in the listing order x, y, z
-  // for ties: when lx == ly the two trade places first, so that equal
-  // eigenvalues keep their arrow order (lambda I and 0 give V = I).
-  if (lx == ly) {
-    const Vec3 tu = ux;
-    ux = uy;
-    uy = tu;
-  }
-  double l0, l1, l2;
-  Vec3 v0, v1, v2;
-  if (lz < ly) {
-    l0 = lz; l1 = ly; l2 = lx; v0 = uz; v1 = uy; v2 = ux;
-  } else if (lz < lx) {
-    l0 = ly; l1 = lz; l2 = lx; v0 = uy; v1 = uz; v2 = ux;
-  } else {
-    l0 = ly; l1 = lx; l2 = lz; v0 = uy; v1 = ux; v2 = uz;
-  }
   lam[0] = __builtin_amdgcn_ldexp(l0, e);
   lam[1] = __builtin_amdgcn_ldexp(l1, e);
   lam[2] = __builtin_amdgcn_ldexp(l2, e);

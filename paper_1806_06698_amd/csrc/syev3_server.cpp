@@ -1,0 +1,614 @@
+// syev3_server.cpp -- continuous-batching server for batched 3x3 solves.
+//
+// Clients acquire a request (admission: a free slot and room in the device
+// pool, which is one hipMalloc of the HBM budget carved by a first-fit free
+// list), fill its input on the device, and submit it.  A scheduler thread
+// forms ticks from everything submitted so far: a table of the requests
+// (segments) is written to pinned host memory and the tick is launched on
+// one of `max_inflight_ticks` streams, either as a graph captured once per
+// tick slot (copy of the table to the device, then the persistent segment
+// kernel) or as the same two operations issued directly.  While some ticks
+// run, newly submitted requests go into the next free slot's tick, so work
+// of different ticks overlaps on the device.  Completion is observed by
+// polling each tick's event; results are then readable and the request can
+// be released, freeing its memory for waiting requests.
+//
+// The per-matrix arithmetic of the segment kernel is that of the batched
+// kernels, so each request's results are bitwise the same as a separate
+// batched_syev3 call on the same input, whatever else shares its tick.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <random>
+#include <thread>
+#include <vector>
+
+#include "syev3.h"
+#include "syev3_internal.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double seconds_since(Clock::time_point t0, Clock::time_point t) {
+  return std::chrono::duration<double>(t - t0).count();
+}
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over [0, size) with coalescing frees.
+class PoolAllocator {
+ public:
+  explicit PoolAllocator(size_t size) : size_(size) { free_[0] = size; }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t noff = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[noff] = rest;
+        in_use_ += bytes;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    in_use_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t in_use() const { return in_use_; }
+  size_t size() const { return size_; }
+
+ private:
+  size_t size_;
+  size_t in_use_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+enum ReqState { kFree = 0, kAdmitted, kQueued, kRunning, kDone };
+
+struct Request {
+  int state = kFree;
+  bool failed = false;  // its tick could not be launched
+  uint32_t gen = 0;
+  int64_t n = 0;
+  int dtype = 0;
+  bool vecs = true;
+  size_t off = 0, bytes = 0;
+  void* A = nullptr;
+  void* lam = nullptr;
+  void* V = nullptr;
+  hipEvent_t ready = nullptr;
+  Clock::time_point t_submit, t_done;
+};
+
+struct TickSlot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  syev3::TickTable* h_table = nullptr;  // pinned host
+  syev3::TickTable* d_table = nullptr;  // device
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> reqs;
+  bool busy = false;
+};
+
+}  // namespace
+
+struct syev3_server {
+  syev3_server_opts o{};
+  int device = 0;
+  char* pool = nullptr;
+  PoolAllocator* alloc = nullptr;
+  std::vector<Request> req;
+  std::vector<int> free_slots;
+  std::deque<int> queue;
+  std::vector<TickSlot> ticks;
+  size_t table_bytes = 0;
+  int grid_blocks = 0;
+
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done;
+  bool stop = false;
+  std::thread thr;
+
+  syev3_server_stats st{};
+  int busy_ticks = 0;
+  Clock::time_point busy_since;
+  Clock::time_point t0 = Clock::now();
+
+  void scheduler();
+  int launch_tick(int slot);
+};
+
+namespace {
+
+int64_t make_id(int slot, uint32_t gen) { return ((int64_t)gen << 32) | (int64_t)slot; }
+
+Request* lookup(syev3_server* s, int64_t id, int* slot_out) {
+  if (!s || id < 0) return nullptr;
+  const int slot = (int)(id & 0xffffffff);
+  const uint32_t gen = (uint32_t)(id >> 32);
+  if (slot < 0 || slot >= (int)s->req.size()) return nullptr;
+  Request* r = &s->req[slot];
+  if (r->gen != gen || r->state == kFree) return nullptr;
+  if (slot_out) *slot_out = slot;
+  return r;
+}
+
+size_t request_bytes(int64_t n, int dtype, bool vecs) {
+  const size_t es = dtype == SYEV3_F64 ? 8 : 4;
+  return align_up(6 * (size_t)n * es) + align_up(3 * (size_t)n * es) +
+         (vecs ? align_up(9 * (size_t)n * es) : 0);
+}
+
+}  // namespace
+
+int syev3_server::launch_tick(int slot) {
+  TickSlot& tk = ticks[slot];
+  syev3::TickTable* t = tk.h_table;
+  int nseg = 0;
+  int64_t tiles = 0;
+  tk.reqs.clear();
+  while (!queue.empty() && nseg < o.max_segments_per_tick) {
+    const int ri = queue.front();
+    queue.pop_front();
+    Request& r = req[ri];
+    syev3::Segment& sg = t->seg[nseg++];
+    sg.A = r.A;
+    sg.lambda = r.lam;
+    sg.V = r.vecs ? r.V : nullptr;
+    sg.n = r.n;
+    sg.tile_begin = tiles;
+    sg.dtype = r.dtype;
+    sg.flags = 0;
+    tiles += (r.n + syev3::kBlock - 1) / syev3::kBlock;
+    r.state = kRunning;
+    tk.reqs.push_back(ri);
+    if (r.ready) (void)hipStreamWaitEvent(tk.stream, r.ready, 0);
+  }
+  t->nseg = nseg;
+  t->total_tiles = tiles;
+  hipError_t e;
+  if (tk.exec) {
+    e = hipGraphLaunch(tk.exec, tk.stream);
+  } else {
+    e = hipMemcpyAsync(tk.d_table, tk.h_table, table_bytes, hipMemcpyHostToDevice, tk.stream);
+    if (e == hipSuccess) e = syev3::launch_segments(tk.d_table, grid_blocks, tk.stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(tk.done, tk.stream);
+  if (e != hipSuccess) return SYEV3_E_HIP;
+  tk.busy = true;
+  if (busy_ticks++ == 0) busy_since = Clock::now();
+  st.ticks++;
+  st.inflight_ticks_peak = std::max(st.inflight_ticks_peak, busy_ticks);
+  st.segments_per_tick_peak = std::max(st.segments_per_tick_peak, nseg);
+  return SYEV3_OK;
+}
+
+void syev3_server::scheduler() {
+  (void)hipSetDevice(device);
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    // completions
+    bool any_done = false;
+    for (auto& tk : ticks) {
+      if (!tk.busy) continue;
+      const hipError_t q = hipEventQuery(tk.done);
+      if (q == hipErrorNotReady) continue;
+      const auto now = Clock::now();
+      for (int ri : tk.reqs) {
+        Request& r = req[ri];
+        r.state = kDone;
+        r.failed = q != hipSuccess;
+        r.t_done = now;
+        st.completed++;
+        st.matrices_completed += r.n;
+      }
+      tk.reqs.clear();
+      tk.busy = false;
+      if (--busy_ticks == 0) st.busy_seconds += seconds_since(busy_since, now);
+      any_done = true;
+    }
+    // launches: every free tick slot takes the queue's head
+    for (int k = 0; k < (int)ticks.size() && !queue.empty(); ++k) {
+      if (!ticks[k].busy) {
+        if (launch_tick(k) != SYEV3_OK) {
+          // the tick's requests complete as failed; the slot stays idle
+          const auto now = Clock::now();
+          for (int ri : ticks[k].reqs) {
+            req[ri].state = kDone;
+            req[ri].failed = true;
+            req[ri].t_done = now;
+          }
+          ticks[k].reqs.clear();
+          any_done = true;
+        }
+      }
+    }
+    if (any_done) cv_done.notify_all();
+    if (stop && busy_ticks == 0 && queue.empty()) break;
+    if (busy_ticks > 0) {
+      // poll completions at a short period while work is on the device
+      cv_sched.wait_for(lk, std::chrono::microseconds(20));
+    } else {
+      cv_sched.wait(lk, [&] { return stop || !queue.empty(); });
+    }
+  }
+}
+
+extern "C" {
+
+void syev3_server_default_opts(syev3_server_opts* o) {
+  if (!o) return;
+  o->hbm_budget_bytes = 64ull << 30;
+  o->max_requests = 4096;
+  o->max_inflight_ticks = 4;
+  o->max_segments_per_tick = 256;
+  o->grid_blocks = 0;
+  o->use_graphs = 1;
+}
+
+int syev3_server_create(const syev3_server_opts* opts, syev3_server** out) {
+  if (!out) return SYEV3_E_NULL;
+  *out = nullptr;
+  syev3_server_opts o;
+  syev3_server_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.hbm_budget_bytes < kAlign || o.max_requests < 1 || o.max_inflight_ticks < 1 ||
+      o.max_inflight_ticks > 64 || o.max_segments_per_tick < 1 ||
+      o.max_segments_per_tick > syev3::kMaxSegmentsPerTick || o.grid_blocks < 0)
+    return SYEV3_E_N;
+  syev3_server* s = new (std::nothrow) syev3_server();
+  if (!s) return SYEV3_E_HIP;
+  s->o = o;
+  int rc = SYEV3_OK;
+  if (hipGetDevice(&s->device) != hipSuccess) rc = SYEV3_E_HIP;
+  if (rc == SYEV3_OK && hipMalloc((void**)&s->pool, o.hbm_budget_bytes) != hipSuccess) {
+    s->pool = nullptr;
+    rc = SYEV3_E_BUDGET;
+  }
+  s->alloc = new PoolAllocator(o.hbm_budget_bytes);
+  s->req.resize(o.max_requests);
+  for (int k = o.max_requests - 1; k >= 0; --k) s->free_slots.push_back(k);
+  s->table_bytes = syev3::tick_table_bytes(o.max_segments_per_tick);
+  s->grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : syev3::device_cu_count() * 8;
+  s->ticks.resize(o.max_inflight_ticks);
+  for (auto& tk : s->ticks) {
+    if (rc != SYEV3_OK) break;
+    if (hipStreamCreateWithFlags(&tk.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&tk.done, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&tk.h_table, s->table_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&tk.d_table, s->table_bytes) != hipSuccess) {
+      rc = SYEV3_E_HIP;
+      break;
+    }
+    std::memset(tk.h_table, 0, s->table_bytes);
+    if (o.use_graphs) {
+      // capture: table copy, then the segment kernel; replayed per tick
+      bool ok = hipStreamBeginCapture(tk.stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        ok = hipMemcpyAsync(tk.d_table, tk.h_table, s->table_bytes, hipMemcpyHostToDevice,
+                            tk.stream) == hipSuccess;
+        ok = ok && syev3::launch_segments(tk.d_table, s->grid_blocks, tk.stream) == hipSuccess;
+        const bool ended = hipStreamEndCapture(tk.stream, &tk.graph) == hipSuccess;
+        ok = ok && ended;
+      }
+      ok = ok && hipGraphInstantiate(&tk.exec, tk.graph, nullptr, nullptr, 0) == hipSuccess;
+      if (!ok) rc = SYEV3_E_HIP;
+    }
+  }
+  if (rc != SYEV3_OK) {
+    syev3_server_destroy(s);
+    return rc;
+  }
+  s->thr = std::thread([s] { s->scheduler(); });
+  *out = s;
+  return SYEV3_OK;
+}
+
+int syev3_server_destroy(syev3_server* s) {
+  if (!s) return SYEV3_E_STATE;
+  if (s->thr.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+    }
+    s->cv_sched.notify_all();
+    s->thr.join();
+  }
+  for (auto& tk : s->ticks) {
+    if (tk.stream) (void)hipStreamSynchronize(tk.stream);
+    if (tk.exec) (void)hipGraphExecDestroy(tk.exec);
+    if (tk.graph) (void)hipGraphDestroy(tk.graph);
+    if (tk.d_table) (void)hipFree(tk.d_table);
+    if (tk.h_table) (void)hipHostFree(tk.h_table);
+    if (tk.done) (void)hipEventDestroy(tk.done);
+    if (tk.stream) (void)hipStreamDestroy(tk.stream);
+  }
+  if (s->pool) (void)hipFree(s->pool);
+  delete s->alloc;
+  delete s;
+  return SYEV3_OK;
+}
+
+int64_t syev3_server_acquire(syev3_server* s, int64_t n, int dtype, int want_vectors,
+                             syev3_request_buffers* bufs) {
+  if (!s || !bufs) return SYEV3_E_NULL;
+  if (n < 1 || n > ((int64_t)1 << 40)) return SYEV3_E_N;
+  if (dtype != SYEV3_F64 && dtype != SYEV3_F32_REFINE) return SYEV3_E_DTYPE;
+  const bool vecs = want_vectors != 0;
+  const size_t bytes = request_bytes(n, dtype, vecs);
+  if (bytes > s->o.hbm_budget_bytes) return SYEV3_E_BUDGET;
+  std::lock_guard<std::mutex> lk(s->mu);
+  size_t off = 0;
+  if (s->free_slots.empty() || !s->alloc->alloc(bytes, &off)) {
+    s->st.acquire_rejections++;
+    return SYEV3_E_AGAIN;
+  }
+  const int slot = s->free_slots.back();
+  s->free_slots.pop_back();
+  Request& r = s->req[slot];
+  const size_t es = dtype == SYEV3_F64 ? 8 : 4;
+  r.state = kAdmitted;
+  r.n = n;
+  r.dtype = dtype;
+  r.vecs = vecs;
+  r.off = off;
+  r.bytes = bytes;
+  r.A = s->pool + off;
+  r.lam = s->pool + off + align_up(6 * (size_t)n * es);
+  r.V = vecs ? s->pool + off + align_up(6 * (size_t)n * es) + align_up(3 * (size_t)n * es)
+             : nullptr;
+  r.ready = nullptr;
+  r.failed = false;
+  s->st.pool_bytes_in_use = s->alloc->in_use();
+  s->st.pool_bytes_peak = std::max<uint64_t>(s->st.pool_bytes_peak, s->alloc->in_use());
+  bufs->A = r.A;
+  bufs->lambda = r.lam;
+  bufs->V = r.V;
+  bufs->n = n;
+  bufs->dtype = dtype;
+  return make_id(slot, r.gen);
+}
+
+int syev3_server_submit(syev3_server* s, int64_t id, hipEvent_t ready) {
+  if (!s) return SYEV3_E_STATE;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    int slot;
+    Request* r = lookup(s, id, &slot);
+    if (!r || r->state != kAdmitted) return SYEV3_E_STATE;
+    r->state = kQueued;
+    r->ready = ready;
+    r->t_submit = Clock::now();
+    s->queue.push_back(slot);
+    s->st.submitted++;
+  }
+  s->cv_sched.notify_one();
+  return SYEV3_OK;
+}
+
+int syev3_server_poll(syev3_server* s, int64_t id, double* latency_s) {
+  if (!s) return SYEV3_E_STATE;
+  std::lock_guard<std::mutex> lk(s->mu);
+  Request* r = lookup(s, id, nullptr);
+  if (!r || r->state == kAdmitted) return SYEV3_E_STATE;
+  if (r->state != kDone) return 0;
+  if (r->failed) return SYEV3_E_HIP;
+  if (latency_s) *latency_s = seconds_since(r->t_submit, r->t_done);
+  return 1;
+}
+
+int syev3_server_wait(syev3_server* s, int64_t id, double timeout_s, double* latency_s) {
+  if (!s) return SYEV3_E_STATE;
+  std::unique_lock<std::mutex> lk(s->mu);
+  Request* r = lookup(s, id, nullptr);
+  if (!r || r->state == kAdmitted) return SYEV3_E_STATE;
+  auto done = [&] { return r->state == kDone; };
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, done);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
+    return SYEV3_E_TIMEOUT;
+  }
+  if (r->failed) return SYEV3_E_HIP;
+  if (latency_s) *latency_s = seconds_since(r->t_submit, r->t_done);
+  return 1;
+}
+
+int syev3_server_release(syev3_server* s, int64_t id) {
+  if (!s) return SYEV3_E_STATE;
+  std::lock_guard<std::mutex> lk(s->mu);
+  int slot;
+  Request* r = lookup(s, id, &slot);
+  if (!r || (r->state != kDone && r->state != kAdmitted)) return SYEV3_E_STATE;
+  s->alloc->release(r->off, r->bytes);
+  s->st.pool_bytes_in_use = s->alloc->in_use();
+  r->state = kFree;
+  r->gen++;
+  s->free_slots.push_back(slot);
+  return SYEV3_OK;
+}
+
+int syev3_server_get_stats(syev3_server* s, syev3_server_stats* out) {
+  if (!s || !out) return SYEV3_E_NULL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *out = s->st;
+  if (s->busy_ticks > 0) out->busy_seconds += seconds_since(s->busy_since, Clock::now());
+  return SYEV3_OK;
+}
+
+int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
+                         syev3_loadgen_result* out) {
+  if (!s || !o || !out) return SYEV3_E_NULL;
+  const bool closed = o->qps == 0.0;
+  if (!(o->qps >= 0) || (closed && o->closed_concurrency < 1) || !(o->duration_s > 0) ||
+      o->src_n < 1 || !o->src_f64 || !o->src_f32 || !(o->max_log2_n >= 0))
+    return SYEV3_E_N;
+  std::memset(out, 0, sizeof(*out));
+  hipStream_t prod = nullptr;
+  if (hipStreamCreateWithFlags(&prod, hipStreamNonBlocking) != hipSuccess) return SYEV3_E_HIP;
+  const int nslots = s->o.max_requests;
+  std::vector<hipEvent_t> ev(nslots, nullptr);
+  for (auto& e : ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (auto& f : ev) if (f) (void)hipEventDestroy(f);
+      (void)hipStreamDestroy(prod);
+      return SYEV3_E_HIP;
+    }
+  }
+  std::mt19937_64 rng(o->seed);
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  std::exponential_distribution<double> gap(closed ? 1.0 : o->qps);
+  struct Arrival {
+    double t;
+    int64_t n;
+    int dtype;
+  };
+  struct Live {
+    int64_t id;
+    double t_arrival;
+    int64_t n;
+  };
+  std::deque<Arrival> waiting;
+  std::vector<Live> live;
+  std::vector<double> lat;
+  double admit_wait_sum = 0.0;
+  int64_t admitted = 0;
+  syev3_server_stats st0{};
+  syev3_server_get_stats(s, &st0);
+  const auto t0 = Clock::now();
+  double next_t = closed ? 0.0 : gap(rng);
+  double last_done = 0.0;
+  int rc = SYEV3_OK;
+  auto draw = [&](double t) {
+    Arrival a;
+    a.t = t;
+    a.n = std::max<int64_t>(1, std::min<int64_t>(o->src_n,
+                                                 (int64_t)std::floor(std::exp2(U(rng) * o->max_log2_n))));
+    a.dtype = U(rng) < o->frac_f32 ? SYEV3_F32_REFINE : SYEV3_F64;
+    return a;
+  };
+  for (;;) {
+    const double now = seconds_since(t0, Clock::now());
+    if (closed) {
+      if (now >= o->duration_s) next_t = o->duration_s;
+      while (now < o->duration_s &&
+             (int64_t)(live.size() + waiting.size()) < o->closed_concurrency)
+        waiting.push_back(draw(now));
+    } else {
+      while (next_t <= now && next_t < o->duration_s) {
+        waiting.push_back(draw(next_t));
+        next_t += gap(rng);
+      }
+    }
+    // admit in arrival order
+    while (!waiting.empty()) {
+      const Arrival& a = waiting.front();
+      syev3_request_buffers b;
+      const int64_t id = syev3_server_acquire(s, a.n, a.dtype, o->want_vectors, &b);
+      if (id == SYEV3_E_AGAIN) break;
+      if (id < 0) { rc = (int)id; break; }
+      const size_t es = a.dtype == SYEV3_F64 ? 8 : 4;
+      const char* src = (const char*)(a.dtype == SYEV3_F64 ? o->src_f64 : o->src_f32);
+      const int64_t off = (int64_t)(U(rng) * (double)(o->src_n - a.n + 1));
+      const int slot = (int)(id & 0xffffffff);
+      if (hipMemcpy2DAsync(b.A, (size_t)a.n * es, src + (size_t)off * es, (size_t)o->src_n * es,
+                           (size_t)a.n * es, 6, hipMemcpyDeviceToDevice, prod) != hipSuccess ||
+          hipEventRecord(ev[slot], prod) != hipSuccess) {
+        rc = SYEV3_E_HIP;
+        break;
+      }
+      if ((rc = syev3_server_submit(s, id, ev[slot])) != SYEV3_OK) break;
+      admit_wait_sum += seconds_since(t0, Clock::now()) - a.t;
+      admitted++;
+      live.push_back(Live{id, a.t, a.n});
+      waiting.pop_front();
+    }
+    if (rc != SYEV3_OK) break;
+    // completions
+    for (size_t k = 0; k < live.size();) {
+      double l;
+      const int p = syev3_server_poll(s, live[k].id, &l);
+      if (p == 1) {
+        const double tnow = seconds_since(t0, Clock::now());
+        lat.push_back(tnow - live[k].t_arrival);
+        last_done = tnow;
+        out->matrices += live[k].n;
+        out->requests++;
+        syev3_server_release(s, live[k].id);
+        live[k] = live.back();
+        live.pop_back();
+      } else if (p < 0) {
+        rc = p;
+        break;
+      } else {
+        ++k;
+      }
+    }
+    if (rc != SYEV3_OK) break;
+    if (next_t >= o->duration_s && waiting.empty() && live.empty()) break;
+    std::this_thread::yield();
+  }
+  // drain whatever is still live after an error
+  for (auto& lv : live) {
+    (void)syev3_server_wait(s, lv.id, 10.0, nullptr);
+    (void)syev3_server_release(s, lv.id);
+  }
+  (void)hipStreamSynchronize(prod);
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  (void)hipStreamDestroy(prod);
+  if (rc != SYEV3_OK) return rc;
+  std::sort(lat.begin(), lat.end());
+  auto pct = [&](double q) {
+    if (lat.empty()) return 0.0;
+    const size_t i = std::min(lat.size() - 1, (size_t)std::floor(q * (double)(lat.size() - 1) + 0.5));
+    return lat[i];
+  };
+  double sum = 0.0;
+  for (double x : lat) sum += x;
+  syev3_server_stats st1{};
+  syev3_server_get_stats(s, &st1);
+  out->elapsed_s = last_done;
+  out->matrices_per_s = last_done > 0 ? (double)out->matrices / last_done : 0.0;
+  out->requests_per_s = last_done > 0 ? (double)out->requests / last_done : 0.0;
+  out->lat_p50_s = pct(0.50);
+  out->lat_p90_s = pct(0.90);
+  out->lat_p99_s = pct(0.99);
+  out->lat_p999_s = pct(0.999);
+  out->lat_max_s = lat.empty() ? 0.0 : lat.back();
+  out->lat_mean_s = lat.empty() ? 0.0 : sum / (double)lat.size();
+  out->admit_wait_mean_s = admitted ? admit_wait_sum / (double)admitted : 0.0;
+  out->ticks = st1.ticks - st0.ticks;
+  out->mean_segments_per_tick =
+      out->ticks ? (double)(st1.submitted - st0.submitted) / (double)out->ticks : 0.0;
+  out->inflight_ticks_peak = st1.inflight_ticks_peak;
+  out->pool_bytes_peak = st1.pool_bytes_peak;
+  return SYEV3_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,173 @@
+"""Python handle on the library's continuous-batching server (C ABI
+syev3_server_*).  The scheduling, pool, graphs and load generator are native;
+this module only marshals arguments."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import RequestBuffers, ServerOpts, ServerStats
+
+
+class LoadgenOpts(ctypes.Structure):
+    _fields_ = [("qps", ctypes.c_double), ("closed_concurrency", ctypes.c_int32),
+                ("duration_s", ctypes.c_double),
+                ("max_log2_n", ctypes.c_double), ("frac_f32", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("src_f64", ctypes.c_void_p),
+                ("src_f32", ctypes.c_void_p), ("src_n", ctypes.c_int64),
+                ("want_vectors", ctypes.c_int32)]
+
+
+class LoadgenResult(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("matrices", ctypes.c_int64),
+                ("elapsed_s", ctypes.c_double), ("matrices_per_s", ctypes.c_double),
+                ("requests_per_s", ctypes.c_double),
+                ("lat_p50_s", ctypes.c_double), ("lat_p90_s", ctypes.c_double),
+                ("lat_p99_s", ctypes.c_double), ("lat_p999_s", ctypes.c_double),
+                ("lat_max_s", ctypes.c_double), ("lat_mean_s", ctypes.c_double),
+                ("admit_wait_mean_s", ctypes.c_double), ("ticks", ctypes.c_int64),
+                ("mean_segments_per_tick", ctypes.c_double),
+                ("inflight_ticks_peak", ctypes.c_int32),
+                ("pool_bytes_peak", ctypes.c_uint64)]
+
+
+def _bind(L):
+    if getattr(L, "_serve_bound", False):
+        return L
+    L.syev3_server_loadgen.argtypes = [ctypes.c_void_p, ctypes.POINTER(LoadgenOpts),
+                                       ctypes.POINTER(LoadgenResult)]
+    L.syev3_server_loadgen.restype = ctypes.c_int
+    L._serve_bound = True
+    return L
+
+
+class Request:
+    """An admitted request: device tensors over the server's pool."""
+
+    def __init__(self, server, rid, bufs: RequestBuffers, dtype):
+        self.server, self.id, self.n = server, rid, bufs.n
+        tdt = torch.float64 if bufs.dtype == _lib.F64 else torch.float32
+        es = 8 if tdt == torch.float64 else 4
+        self.A = _tensor_at(bufs.A, (6, bufs.n), tdt, es)
+        self.lam = _tensor_at(bufs.lam, (3, bufs.n), tdt, es)
+        self.V = _tensor_at(bufs.V, (9, bufs.n), tdt, es) if bufs.V else None
+
+
+def _tensor_at(ptr, shape, dtype, esize):
+    """A torch view of device memory owned by the server (no copy)."""
+    numel = shape[0] * shape[1]
+    dev = torch.cuda.current_device()
+    class _Holder:
+        __cuda_array_interface__ = {
+            "shape": shape, "typestr": "<f8" if esize == 8 else "<f4",
+            "data": (int(ptr), False), "version": 3, "strides": None}
+    return torch.as_tensor(_Holder(), device=f"cuda:{dev}").view(shape) if numel else \
+        torch.empty(shape, dtype=dtype, device=f"cuda:{dev}")
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes=64 << 30, max_requests=4096,
+                 max_inflight_ticks=4, max_segments_per_tick=256, grid_blocks=0,
+                 use_graphs=True):
+        self.L = _bind(_lib.lib())
+        o = ServerOpts()
+        self.L.syev3_server_default_opts(ctypes.byref(o))
+        o.hbm_budget_bytes = hbm_budget_bytes
+        o.max_requests = max_requests
+        o.max_inflight_ticks = max_inflight_ticks
+        o.max_segments_per_tick = max_segments_per_tick
+        o.grid_blocks = grid_blocks
+        o.use_graphs = 1 if use_graphs else 0
+        h = ctypes.c_void_p()
+        _lib.check(self.L.syev3_server_create(ctypes.byref(o), ctypes.byref(h)),
+                   "syev3_server_create")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _lib.check(self.L.syev3_server_destroy(self.h), "syev3_server_destroy")
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def acquire(self, n, dtype=_lib.F64, vectors=True):
+        """Request or None when the pool/slots are full now (E_AGAIN)."""
+        b = RequestBuffers()
+        rid = self.L.syev3_server_acquire(self.h, n, dtype, 1 if vectors else 0,
+                                          ctypes.byref(b))
+        if rid == _lib.E_AGAIN:
+            return None
+        _lib.check(rid, "syev3_server_acquire")
+        return Request(self, rid, b, dtype)
+
+    def submit(self, req: Request, ready_event=None):
+        ev = ctypes.c_void_p(ready_event.cuda_event if ready_event is not None else 0)
+        _lib.check(self.L.syev3_server_submit(self.h, req.id, ev), "syev3_server_submit")
+
+    def poll(self, req):
+        lat = ctypes.c_double()
+        rc = _lib.check(self.L.syev3_server_poll(self.h, req.id, ctypes.byref(lat)),
+                        "syev3_server_poll")
+        return lat.value if rc == 1 else None
+
+    def wait(self, req, timeout_s=-1.0):
+        lat = ctypes.c_double()
+        _lib.check(self.L.syev3_server_wait(self.h, req.id, timeout_s, ctypes.byref(lat)),
+                   "syev3_server_wait")
+        return lat.value
+
+    def release(self, req):
+        _lib.check(self.L.syev3_server_release(self.h, req.id), "syev3_server_release")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _lib.check(self.L.syev3_server_get_stats(self.h, ctypes.byref(s)), "stats")
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def loadgen(self, src_f64, src_f32, qps, duration_s, max_log2_n=20.0,
+                frac_f32=0.5, seed=0, vectors=True, concurrency=0) -> dict:
+        """qps > 0: open-loop Poisson arrivals; qps == 0: closed loop with
+        `concurrency` requests in flight."""
+        o = LoadgenOpts(qps=qps, closed_concurrency=concurrency,
+                        duration_s=duration_s, max_log2_n=max_log2_n,
+                        frac_f32=frac_f32, seed=seed, src_f64=src_f64.data_ptr(),
+                        src_f32=src_f32.data_ptr(), src_n=src_f64.shape[1],
+                        want_vectors=1 if vectors else 0)
+        r = LoadgenResult()
+        _lib.check(self.L.syev3_server_loadgen(self.h, ctypes.byref(o), ctypes.byref(r)),
+                   "syev3_server_loadgen")
+        return {f: getattr(r, f) for f, _ in r._fields_}
+
+
+def bench(duration_s=4.0, budget_bytes=64 << 30, seed=3):
+    """Serving measurement: request sizes 2^U(0,20) from the stress mix, 50%
+    FP64 / 50% FP32-storage.  First the saturated rate (closed loop, 64
+    requests in flight), then open-loop Poisson arrivals at 50% and 80% of
+    that rate."""
+    from . import gen
+    src_n = 1 << 20
+    A, _ = gen.stress_mix(src_n, seed=seed, device="cuda")
+    Af = A.float().contiguous()
+    torch.cuda.synchronize()
+    out = {"workload": "Poisson arrivals; n = floor(2^U(0,20)) stress-mix matrices per "
+                       "request; 50% FP64 / 50% FP32-storage; vals+vecs; inputs copied "
+                       "on the device from a resident pool; HBM budget "
+                       f"{budget_bytes / 2**30:.0f} GiB",
+           "latency": "arrival to observed completion (includes waiting for admission)"}
+    with Server(hbm_budget_bytes=budget_bytes) as srv:
+        sat = srv.loadgen(A, Af, qps=0.0, concurrency=64,
+                          duration_s=min(2.0, duration_s), seed=seed)
+        out["closed_loop_64_in_flight"] = sat
+        rate = sat["requests_per_s"]
+        for rho in (0.5, 0.8):
+            r = srv.loadgen(A, Af, qps=rho * rate, duration_s=duration_s, seed=seed + 1)
+            r["offered_qps"] = rho * rate
+            out[f"open_loop_{int(rho * 100)}pct"] = r
+        out["server_stats"] = srv.stats()
+    return out

@@ -83,3 +83,21 @@ def test_python_binding_refuses_cpu_tensors():
     import paper_1806_06698_amd as s3
     with pytest.raises(ValueError):
         s3.syev3(torch.zeros(6, 4, dtype=torch.float64))
+
+
+def test_server_rejects_bad_options_without_a_gpu(L):
+    from paper_1806_06698_amd import _lib as lb
+    o = lb.ServerOpts()
+    L.syev3_server_default_opts(ctypes.byref(o))
+    assert o.hbm_budget_bytes == 64 << 30 and o.max_inflight_ticks == 4
+    h = ctypes.c_void_p()
+    o.max_requests = 0
+    assert L.syev3_server_create(ctypes.byref(o), ctypes.byref(h)) == -1
+    L.syev3_server_default_opts(ctypes.byref(o))
+    o.max_segments_per_tick = 100000
+    assert L.syev3_server_create(ctypes.byref(o), ctypes.byref(h)) == -1
+    assert L.syev3_server_create(ctypes.byref(o), None) == -2
+    b = lb.RequestBuffers()
+    assert L.syev3_server_acquire(None, 10, 0, 1, ctypes.byref(b)) == -2
+    assert L.syev3_server_submit(None, 0, None) == -10
+    assert L.syev3_server_release(None, 0) == -10

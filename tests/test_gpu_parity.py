@@ -116,6 +116,12 @@ def test_info_reports_branches_and_iterations():
     print(f"branch agreement {agree:.6f}; GPU branches {np.bincount(br, minlength=5)}; "
           f"BG evaluations mu: mean {it_mu[br == 4].mean():.2f} max {it_mu.max()}, "
           f"nu: mean {it_nu[br == 4].mean():.2f} max {it_nu.max()}", flush=True)
+    # the loop of a wavefront runs until its slowest lane is done
+    trips = np.maximum(it_mu, it_nu)
+    w = len(trips) // 64 * 64
+    wave_max = trips[:w].reshape(-1, 64).max(1)
+    print(f"zero-finder trips per wavefront: mean {wave_max.mean():.2f} max {wave_max.max()}",
+          flush=True)
     assert agree > 0.999
     assert np.all(br[cat.numpy() == gen.CAT_DIAGONAL] == 2)
     assert it_mu.max() < 32 and it_nu.max() < 32

@@ -1,0 +1,149 @@
+"""Serving: continuous batching through the library's server (C ABI
+syev3_server_*).  Each request's result must be bitwise the one a separate
+batched_syev3 call gives on the same input, whatever shares its tick;
+admission must respect the HBM budget; graph-launched ticks must stay
+correct over many replays with other GPU work in between."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1806_06698_amd as s3
+from gpu_common import need_gpu
+from paper_1806_06698_amd import gen, serve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.fixture(scope="module")
+def source():
+    A, _ = gen.stress_mix(1 << 21, seed=7, device="cuda")
+    return A, A.float().contiguous()
+
+
+def _fill(req, src, off):
+    """Copy n source matrices into the request's input (on the current
+    stream); returns the event that marks them ready."""
+    n = req.n
+    req.A.copy_(src[:, off:off + n])
+    ev = torch.cuda.Event()
+    ev.record()
+    return ev
+
+
+def _reference(req):
+    lam, V = s3.syev3(req.A.clone(), vectors=req.V is not None)
+    return lam, V
+
+
+def _check_bitwise(req):
+    lam, V = _reference(req)
+    torch.cuda.synchronize()
+    assert torch.equal(lam, req.lam), f"lambda differs for n={req.n}"
+    if V is not None:
+        assert torch.equal(V, req.V), f"V differs for n={req.n}"
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_each_result_same_alone_and_in_the_mix(source, use_graphs):
+    A64, A32 = source
+    rng = np.random.default_rng(1)
+    sizes = [1, 63, 64, 255, 256, 257, 1000, 4097, 50_000, 123_457, 1 << 20]
+    with serve.Server(hbm_budget_bytes=2 << 30, use_graphs=use_graphs,
+                      max_inflight_ticks=3) as srv:
+        reqs = []
+        for k, n in enumerate(sizes):
+            dt = s3.F32_REFINE if k % 2 else s3.F64
+            vec = k % 5 != 4
+            r = srv.acquire(n, dt, vectors=vec)
+            assert r is not None
+            off = int(rng.integers(0, (1 << 21) - n))
+            ev = _fill(r, A32 if dt == s3.F32_REFINE else A64, off)
+            srv.submit(r, ev)
+            reqs.append(r)
+        for r in reqs:
+            lat = srv.wait(r, timeout_s=60.0)
+            assert lat >= 0.0
+        for r in reqs:
+            _check_bitwise(r)
+            srv.release(r)
+        st = srv.stats()
+        assert st["completed"] == len(sizes)
+        assert st["pool_bytes_in_use"] == 0
+
+
+def test_many_ticks_with_eager_work_between_replays(source):
+    A64, A32 = source
+    rng = np.random.default_rng(2)
+    scratch = torch.zeros(1 << 20, device="cuda")
+    with serve.Server(hbm_budget_bytes=1 << 30, max_inflight_ticks=2) as srv:
+        for it in range(40):
+            reqs = []
+            for _ in range(int(rng.integers(1, 5))):
+                n = int(2 ** rng.uniform(0, 16))
+                dt = s3.F64 if rng.random() < 0.5 else s3.F32_REFINE
+                r = srv.acquire(n, dt)
+                ev = _fill(r, A64 if dt == s3.F64 else A32, int(rng.integers(0, 1 << 20)))
+                srv.submit(r, ev)
+                reqs.append(r)
+            # the program's own eager work and a synchronisation between ticks
+            scratch.add_(1.0).mul_(0.5)
+            torch.cuda.synchronize()
+            for r in reqs:
+                srv.wait(r, timeout_s=60.0)
+                _check_bitwise(r)
+                srv.release(r)
+        assert srv.stats()["ticks"] >= 40
+
+
+def test_admission_by_budget():
+    budget = 64 << 20
+    with serve.Server(hbm_budget_bytes=budget, max_requests=64) as srv:
+        with pytest.raises(s3.Syev3Error) as ei:
+            srv.acquire(1 << 20, s3.F64)          # 151 MB > 64 MiB: never fits
+        assert ei.value.code == -8
+        held = []
+        while True:
+            r = srv.acquire(100_000, s3.F64)      # 14.4 MB each
+            if r is None:
+                break
+            held.append(r)
+        assert len(held) == 4                     # 4 * 14.4 MB fit in 64 MiB
+        assert srv.stats()["acquire_rejections"] >= 1
+        srv.release(held.pop())
+        r = srv.acquire(100_000, s3.F64)
+        assert r is not None
+        held.append(r)
+        for r in held:
+            srv.release(r)
+        assert srv.stats()["pool_bytes_in_use"] == 0
+
+
+def test_request_state_errors(source):
+    A64, _ = source
+    with serve.Server(hbm_budget_bytes=64 << 20) as srv:
+        r = srv.acquire(1000, s3.F64)
+        with pytest.raises(s3.Syev3Error):
+            srv.poll(r)                           # not submitted yet
+        srv.submit(r, _fill(r, A64, 0))
+        with pytest.raises(s3.Syev3Error):
+            srv.submit(r)                         # twice
+        srv.wait(r, 60.0)
+        srv.release(r)
+        with pytest.raises(s3.Syev3Error):
+            srv.release(r)                        # released id is stale
+
+
+def test_loadgen_short_run(source):
+    A64, A32 = source
+    with serve.Server(hbm_budget_bytes=4 << 30) as srv:
+        res = srv.loadgen(A64[:, :1 << 18].contiguous(), A32[:, :1 << 18].contiguous(),
+                          qps=2000.0, duration_s=0.5, max_log2_n=14, seed=5)
+    print(res, flush=True)
+    assert res["requests"] > 100
+    assert 0 < res["lat_p50_s"] <= res["lat_p99_s"] <= res["lat_max_s"]
+    assert res["matrices"] > 0 and res["ticks"] > 0
