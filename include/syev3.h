@@ -25,6 +25,9 @@
  *   SYEV3_AOS  array of structures, packed: A[6*i + k], lambda[3*i + j],
  *              V[9*i + 3*r + c] (row-major 3x3, column c is eigenvector c,
  *              as torch.linalg.eigh).  ld must be 0.
+ *   SYEV3_AOS9 as SYEV3_AOS, but the input is the full matrix,
+ *              A[9*i + 3*r + c]; entries below the diagonal are not read.
+ *              V may be the same pointer as A (in place).
  * Eigenvalues are in ascending order; column c of V belongs to lambda c.
  * The sign of each eigenvector, and the basis inside an eigenspace of a
  * repeated eigenvalue, are whatever the method produces.
@@ -66,6 +69,8 @@ extern "C" {
 /* layouts */
 #define SYEV3_SOA 0
 #define SYEV3_AOS 1
+#define SYEV3_AOS9 2   /* input n x 9: full row-major 3x3 matrices (only the
+                          upper triangle is read); outputs as SYEV3_AOS */
 
 /* flags for batched_syev3_ex */
 #define SYEV3_FLAG_SIMPLIFIED_DEFLATION 1u /* the simplified test of Sec. 1.1,
@@ -108,6 +113,15 @@ int batched_syev3(int64_t n, const void* A_upper6, void* lambda, void* V,
 int batched_syev3_ex(int64_t n, const void* A, int64_t ld, int layout,
                      void* lambda, void* V, int dtype, uint32_t flags,
                      hipStream_t stream);
+
+/*
+ * batched_syev3_inplace -- for callers that keep full 3x3 matrices (one per
+ * finite element, say): A is n x 9 row-major (SYEV3_AOS9) and is overwritten
+ * by the eigenvectors (column c of each 3x3 is eigenvector c); lambda is n x 3.
+ * Same as batched_syev3_ex(n, A, 0, SYEV3_AOS9, lambda, A, dtype, 0, stream).
+ */
+int batched_syev3_inplace(int64_t n, void* A, void* lambda, int dtype,
+                          hipStream_t stream);
 
 /*
  * batched_syev3_info -- batched_syev3_ex that also writes, per matrix,

@@ -16,11 +16,11 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (AOS, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD,
+from ._lib import (AOS, AOS9, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD,
                    FLAG_SIMPLIFIED_DEFLATION, SOA, Syev3Error)
 
-__all__ = ["syev3", "batched_syev3", "batched_syev3_ex", "batched_syev3_info",
-           "F64", "F32_REFINE", "SOA", "AOS", "FLAG_SIMPLIFIED_DEFLATION",
+__all__ = ["syev3", "syev3_inplace", "batched_syev3", "batched_syev3_ex", "batched_syev3_info",
+           "F64", "F32_REFINE", "SOA", "AOS", "AOS9", "FLAG_SIMPLIFIED_DEFLATION",
            "FLAG_NO_H_GUARD", "FLAG_NEWTON", "Syev3Error", "lib_path"]
 
 lib_path = _lib.LIB_PATH
@@ -70,6 +70,8 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
     and V (9, n) with V[3*r + c, i] = row r of eigenvector c of matrix i.
     layout "aos": A has shape (n, 6), contiguous.  Returns lam (n, 3) and
     V (n, 3, 3) with columns the eigenvectors (as torch.linalg.eigh).
+    layout "aos9": A holds full matrices, (n, 3, 3) or (n, 9), contiguous
+    (only the upper triangle is read); outputs as for "aos".
     float64 input runs the FP64 path; float32 input the FP32-storage path
     with FP64 refinement.  vectors=False skips V.  info=True also returns the
     per-matrix branch and iteration counts (int32).
@@ -94,9 +96,13 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
             if lam.stride(0) != ld or (V is not None and V.stride(0) != ld):
                 raise ValueError("output plane stride must equal the input's")
         lay = SOA
-    elif layout == "aos":
-        if A.dim() != 2 or A.shape[1] != 6 or not A.is_contiguous():
-            raise ValueError("AoS input must be a contiguous (n, 6) tensor")
+    elif layout in ("aos", "aos9"):
+        width = 6 if layout == "aos" else 9
+        if layout == "aos9" and A.dim() == 3 and A.shape[1:] == (3, 3):
+            A = A.reshape(A.shape[0], 9)
+        if A.dim() != 2 or A.shape[1] != width or not A.is_contiguous():
+            raise ValueError(f"{layout} input must be a contiguous (n, {width}) tensor"
+                             + (" or (n, 3, 3)" if width == 9 else ""))
         n = A.shape[0]
         ld = 0
         if out is None:
@@ -104,7 +110,7 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
             V = torch.empty((n, 3, 3), dtype=A.dtype, device=A.device) if vectors else None
         else:
             lam, V = out
-        lay = AOS
+        lay = AOS if layout == "aos" else AOS9
     else:
         raise ValueError(f"unknown layout {layout!r}")
     inf = torch.empty(n, dtype=torch.int32, device=A.device) if info else None
@@ -115,3 +121,17 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
     if info:
         return lam, V, inf
     return lam, V
+
+
+def syev3_inplace(A: torch.Tensor, *, stream=None) -> torch.Tensor:
+    """Full matrices A (n, 3, 3), contiguous, are overwritten by their
+    eigenvectors (columns); returns the eigenvalues (n, 3), ascending."""
+    if not A.is_cuda:
+        raise ValueError("A must be a GPU tensor (the solver has no CPU path)")
+    if A.dim() != 3 or A.shape[1:] != (3, 3) or not A.is_contiguous():
+        raise ValueError("A must be a contiguous (n, 3, 3) tensor")
+    lam = torch.empty((A.shape[0], 3), dtype=A.dtype, device=A.device)
+    rc = _lib.lib().batched_syev3_inplace(A.shape[0], _ptr(A), _ptr(lam), _dtype_code(A),
+                                          _stream_handle(stream))
+    _lib.check(rc, "batched_syev3_inplace")
+    return lam

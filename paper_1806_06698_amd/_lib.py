@@ -15,6 +15,7 @@ F64 = 0
 F32_REFINE = 1
 SOA = 0
 AOS = 1
+AOS9 = 2
 FLAG_SIMPLIFIED_DEFLATION = 1
 FLAG_NO_H_GUARD = 2
 FLAG_NEWTON = 4
@@ -78,6 +79,8 @@ def lib() -> ctypes.CDLL:
     L.batched_syev3.restype = i32
     L.batched_syev3_ex.argtypes = [i64, vp, i64, i32, vp, vp, i32, u32, vp]
     L.batched_syev3_ex.restype = i32
+    L.batched_syev3_inplace.argtypes = [i64, vp, vp, i32, vp]
+    L.batched_syev3_inplace.restype = i32
     L.batched_syev3_info.argtypes = [i64, vp, i64, i32, vp, vp, i32, u32, vp, vp]
     L.batched_syev3_info.restype = i32
     L.syev3_strerror.argtypes = [i32]

@@ -33,7 +33,8 @@ int check_args(int64_t n, const void* A, int64_t& ld, int layout,
   if (dtype != SYEV3_F64 && dtype != SYEV3_F32_REFINE) return SYEV3_E_DTYPE;
   if (flags & ~SYEV3_FLAGS_ALL) return SYEV3_E_FLAGS;
   if ((flags & SYEV3_FLAG_NEWTON) && dtype != SYEV3_F64) return SYEV3_E_DTYPE;
-  if (layout != SYEV3_SOA && layout != SYEV3_AOS) return SYEV3_E_LAYOUT;
+  if (layout != SYEV3_SOA && layout != SYEV3_AOS && layout != SYEV3_AOS9)
+    return SYEV3_E_LAYOUT;
   if (n < 0) return SYEV3_E_N;
   // every element index (at most 9 planes of ld) must fit in int64 bytes
   const int64_t max_elems = (int64_t)(INT64_MAX / 16 / 9);
@@ -49,10 +50,13 @@ int check_args(int64_t n, const void* A, int64_t& ld, int layout,
   if (n == 0) return SYEV3_OK;
   if (!A || !lambda) return SYEV3_E_NULL;
   const size_t es = dtype == SYEV3_F64 ? sizeof(double) : sizeof(float);
-  const Range ra = span(A, n, ld, layout, 6, es);
+  const Range ra = span(A, n, ld, layout, layout == SYEV3_AOS9 ? 9 : 6, es);
   const Range rl = span(lambda, n, ld, layout, 3, es);
   const Range rv = span(V, n, ld, layout, 9, es);
-  if (overlap(ra, rl) || overlap(ra, rv) || overlap(rl, rv)) return SYEV3_E_ALIAS;
+  // in place: the full-matrix input may be overwritten by V exactly
+  const bool inplace = layout == SYEV3_AOS9 && V == A;
+  if (overlap(ra, rl) || (!inplace && overlap(ra, rv)) || overlap(rl, rv))
+    return SYEV3_E_ALIAS;
   return SYEV3_OK;
 }
 
@@ -68,7 +72,7 @@ int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
   if (info) {
     const Range ri{(uintptr_t)info, (uintptr_t)info + (uintptr_t)n * sizeof(int32_t)};
     const size_t es = dtype == SYEV3_F64 ? sizeof(double) : sizeof(float);
-    if (overlap(ri, span(A, n, ld, layout, 6, es)) ||
+    if (overlap(ri, span(A, n, ld, layout, layout == SYEV3_AOS9 ? 9 : 6, es)) ||
         overlap(ri, span(lambda, n, ld, layout, 3, es)) ||
         overlap(ri, span(V, n, ld, layout, 9, es)))
       return SYEV3_E_ALIAS;
@@ -89,6 +93,11 @@ int batched_syev3(int64_t n, const void* A_upper6, void* lambda, void* V,
                   int dtype, hipStream_t stream) {
   return batched_syev3_info(n, A_upper6, 0, SYEV3_SOA, lambda, V, dtype, 0u,
                             nullptr, stream);
+}
+
+int batched_syev3_inplace(int64_t n, void* A, void* lambda, int dtype,
+                          hipStream_t stream) {
+  return batched_syev3_info(n, A, 0, SYEV3_AOS9, lambda, A, dtype, 0u, nullptr, stream);
 }
 
 const char* syev3_strerror(int code) {

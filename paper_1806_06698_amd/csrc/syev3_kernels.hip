@@ -47,21 +47,31 @@ __global__ __launch_bounds__(kBlock) void k_syev3_soa(
   if (INFO) info[i] = code;
 }
 
-template <typename T, bool VECS, bool INFO>
+// AoS: IN = 6 (unique entries) or 9 (full row-major matrix, upper triangle
+// read).  The whole block is read into LDS before any global store, so the
+// full-matrix input may be overwritten by V (in place).  A is therefore not
+// __restrict__.
+template <typename T, int IN, bool VECS, bool INFO>
 __global__ __launch_bounds__(kBlock) void k_syev3_aos(
-    int64_t n, const T* __restrict__ A, T* __restrict__ lam, T* __restrict__ V,
-    uint32_t flags, int32_t* __restrict__ info) {
+    int64_t n, const T* A, T* __restrict__ lam, T* V, uint32_t flags,
+    int32_t* __restrict__ info) {
   __shared__ T sm[kBlock * 12];
   const int64_t base = (int64_t)blockIdx.x * kBlock;
   const int cnt = (int)((n - base) < kBlock ? (n - base) : kBlock);
   const int t = threadIdx.x;
-  const T* Ab = A + base * 6;
-  for (int k = t; k < cnt * 6; k += kBlock) sm[k] = ld_stream(Ab + k);
+  const T* Ab = A + base * IN;
+  for (int k = t; k < cnt * IN; k += kBlock) sm[k] = ld_stream(Ab + k);
   __syncthreads();
   double a[6];
   if (t < cnt) {
+    if (IN == 6) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) a[k] = (double)sm[6 * t + k];
+      for (int k = 0; k < 6; ++k) a[k] = (double)sm[6 * t + k];
+    } else {
+      const T* m = sm + IN * t;
+      a[0] = (double)m[0]; a[1] = (double)m[1]; a[2] = (double)m[2];
+      a[3] = (double)m[4]; a[4] = (double)m[5]; a[5] = (double)m[8];
+    }
   }
   __syncthreads();
   if (t < cnt) {
@@ -92,8 +102,11 @@ static hipError_t launch_t(int64_t n, const void* A, int64_t ld, int layout,
   if (layout == 0) {
     hipLaunchKernelGGL((k_syev3_soa<T, VECS, INFO>), grid, block, 0, stream, n, ld,
                        (const T*)A, (T*)lambda, (T*)V, flags, info);
+  } else if (layout == 1) {
+    hipLaunchKernelGGL((k_syev3_aos<T, 6, VECS, INFO>), grid, block, 0, stream, n,
+                       (const T*)A, (T*)lambda, (T*)V, flags, info);
   } else {
-    hipLaunchKernelGGL((k_syev3_aos<T, VECS, INFO>), grid, block, 0, stream, n,
+    hipLaunchKernelGGL((k_syev3_aos<T, 9, VECS, INFO>), grid, block, 0, stream, n,
                        (const T*)A, (T*)lambda, (T*)V, flags, info);
   }
   return hipGetLastError();

@@ -59,7 +59,7 @@ def test_bad_arguments_are_rejected(L):
     assert ex(10, A, 0, 0, NUL, VV, 0, 0, S) == -2             # lambda NULL
     assert ex(10, A, 0, 0, LAM, VV, 7, 0, S) == -3             # dtype
     assert ex(10, A, 0, 0, LAM, VV, 1, 4, S) == -3             # Newton needs F64
-    assert ex(10, A, 0, 2, LAM, VV, 0, 0, S) == -4             # layout
+    assert ex(10, A, 0, 3, LAM, VV, 0, 0, S) == -4             # layout
     assert ex(10, A, 5, 0, LAM, VV, 0, 0, S) == -4             # ld < n
     assert ex(10, A, 10, 1, LAM, VV, 0, 0, S) == -4            # AoS needs ld 0
     assert ex(10, A, 0, 0, LAM, VV, 0, 64, S) == -7            # unknown flag
@@ -69,6 +69,11 @@ def test_bad_arguments_are_rejected(L):
     # AoS spans: A is 6n packed elements
     assert ex(10, A, 0, 1, ctypes.c_void_p(0x100000 + 8 * 59), NUL, 0, 0, S) == -5
     assert ex(10, A, 0, 1, ctypes.c_void_p(0x100000 + 8 * 60), NUL, 0, 0, S) != -5
+    # full-matrix AoS: V may be A exactly (in place), not partly
+    assert ex(10, A, 0, 2, ctypes.c_void_p(0x100000 + 8 * 89), NUL, 0, 0, S) == -5
+    assert ex(10, A, 0, 2, LAM, ctypes.c_void_p(0x100000 + 8), 0, 0, S) == -5
+    assert L.batched_syev3_inplace(-1, A, LAM, 0, S) == -1
+    assert L.batched_syev3_inplace(10, A, ctypes.c_void_p(0x100000 + 8 * 10), 0, S) == -5
     # huge n for the grid
     assert ex(1 << 62, A, 0, 0, LAM, VV, 0, 0, S) in (-1, -4)
 

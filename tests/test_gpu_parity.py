@@ -244,3 +244,25 @@ def test_full_size(kind, n, seed):
     assert bool(torch.all(lam[1] >= lam[0]).item() and torch.all(lam[2] >= lam[1]).item())
     del A, lam, V, res, orth
     torch.cuda.empty_cache()
+
+
+def test_full_matrix_layout_and_in_place():
+    A, _ = gen.stress_mix(70_001, 37, "cpu")
+    full = gen.to_full(A).contiguous()
+    # lower triangle is never read
+    garbage = full.clone()
+    garbage[:, 1, 0] = float("nan")
+    garbage[:, 2, 0] = 1e300
+    garbage[:, 2, 1] = -7.0
+    lam_a, V_a = s3.syev3(gen.to_aos(A).cuda(), layout="aos")
+    lam_9, V_9 = s3.syev3(garbage.cuda(), layout="aos9")
+    M = full.cuda()
+    lam_i = s3.syev3_inplace(M)
+    torch.cuda.synchronize()
+    assert torch.equal(lam_a, lam_9) and torch.equal(V_a, V_9)
+    assert torch.equal(lam_a, lam_i) and torch.equal(V_a, M)
+    f32 = full.float().cuda()
+    lam_f = s3.syev3_inplace(f32)
+    lam_fa, V_fa = s3.syev3(gen.to_aos(A).float().cuda(), layout="aos")
+    torch.cuda.synchronize()
+    assert torch.equal(lam_f, lam_fa) and torch.equal(f32, V_fa)
