@@ -214,6 +214,17 @@ int64_t syev3_server_acquire(syev3_server* s, int64_t n, int dtype,
  * on the device, the host does not block. */
 int syev3_server_submit(syev3_server* s, int64_t request, hipEvent_t ready);
 
+/* Host-staged submission: the request's input is copied from host memory
+ * host_A (6 planes of n, SoA, the request's dtype) to its device buffer
+ * before its tick, and the outputs are copied back to host_lambda (3 x n)
+ * and host_V (9 x n, or NULL) after it.  The copies run on per-slot copy
+ * streams apart from the compute streams, so one tick's copies overlap
+ * other ticks' kernels.  The host memory must stay valid and untouched until
+ * the request completes; it should be pinned (hipHostMalloc), otherwise the
+ * copies do not overlap.  Completion (poll/wait) includes the copy back. */
+int syev3_server_submit_host(syev3_server* s, int64_t request, const void* host_A,
+                             void* host_lambda, void* host_V);
+
 /* 1 if the request's results are complete, 0 if not yet, < 0 on error.
  * If done and latency_s is not NULL, it receives submit-to-completion time
  * in seconds. */
@@ -248,10 +259,17 @@ typedef struct {
   double max_log2_n;
   double frac_f32;
   uint64_t seed;
-  const void* src_f64;   /* device, 6 planes of src_n doubles */
-  const void* src_f32;   /* device, 6 planes of src_n floats */
+  const void* src_f64;   /* 6 planes of src_n doubles (device, or pinned
+                            host memory when host_staged) */
+  const void* src_f32;   /* 6 planes of src_n floats (likewise) */
   int64_t src_n;
   int32_t want_vectors;
+  int32_t host_staged;   /* 1: submit through syev3_server_submit_host; a
+                            request's input is the first 6 n values of the
+                            (host) source, its results go to the host sink,
+                            which every request overwrites */
+  void* sink;            /* host_staged: pinned host memory of at least
+                            12 * 2^max_log2_n * 8 bytes for the results */
 } syev3_loadgen_opts;
 
 typedef struct {

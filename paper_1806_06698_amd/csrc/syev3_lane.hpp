@@ -88,12 +88,12 @@ __device__ __forceinline__ double rsqrt2(double x) {
   return 2.0 * h;
 }
 
-// sqrt(x) to ~2^-47 for x >= 0: one Goldschmidt step (0 maps to 0).
+// sqrt(x) to ~2^-47 for normal x > 0: one Goldschmidt step.
 __device__ __forceinline__ double sqrt1(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   const double g = x * y, h = 0.5 * y;
   const double r = __builtin_fma(-g, h, 0.5);
-  return x > 0.0 ? __builtin_fma(g, r, g) : 0.0;
+  return __builtin_fma(g, r, g);
 }
 
 // sqrt(x) to about one ulp: one Goldschmidt step and a residual correction.
@@ -170,13 +170,26 @@ __device__ __forceinline__ Spec spec_eval(const Arrow1& P, double x) {
   return s;
 }
 
-// x0: positive zero of x - gb - (b1^2 + b2^2)/x (the model from +infinity),
-// in the conjugate form when gb < 0.
-__device__ __forceinline__ double bg_start(const Arrow1& P) {
-  const double H = P.b1s + P.b2s;
-  const double g2 = 0.5 * P.gb;
-  const double disc = sqrt2(__builtin_fma(g2, g2, H));
-  return P.gb >= 0.0 ? g2 + disc : ddiv(H, disc - g2);
+// Starting point: the smaller of two upper bounds of the zero.
+//  * x_inf, the zero of x - gb - (b1^2 + b2^2)/x: the first iterate from
+//    +infinity (Sec. 1.4.1); f exceeds that function on (0, inf) because
+//    1/(x + ab) < 1/x.  Tight when ab is small against the zero.
+//  * x_pole, the zero of x - gb - b1^2/x - b2^2/ab: f exceeds it because
+//    1/(x + ab) < 1/ab.  Tight when the zero is small against ab (a zero next
+//    to the pole at 0), where x_inf can be off by many orders of magnitude.
+// Both are positive zeros of x^2 - c x - k, taken in the form without
+// cancellation.  rab = 1/ab.  An iterate that rounding puts left of the zero
+// is caught by the step (f <= 0).
+__device__ __forceinline__ double quad_zero(double c, double k) {
+  const double c2 = 0.5 * c;
+  const double s = dabs(c2) + sqrt1(__builtin_fma(c2, c2, k));
+  return c >= 0.0 ? s : k * rcp1(s);
+}
+
+__device__ __forceinline__ double bg_start(const Arrow1& P, double rab) {
+  const double x_inf = quad_zero(P.gb, P.b1s + P.b2s);
+  const double x_pole = quad_zero(__builtin_fma(P.b2s, rab, P.gb), P.b1s);
+  return __builtin_fmin(x_inf, x_pole);
 }
 
 // One Borges-Gragg step from x (to the right of the zero).  Sets stop when
@@ -185,11 +198,14 @@ __device__ __forceinline__ double bg_start(const Arrow1& P) {
 //     after one Newton step, which from the left converges monotonically
 //     (Sec. 1.4.2);
 //   * the step does not decrease x; returns x;
-//   * f/f' - (x - x_new) <= 2 eps x_new: by the mean-value bound of the
-//     paper's stop test, x - zero < f/f', so x_new - zero < f/f' - (x -
-//     x_new), and x_new is the zero to relative precision 2 eps; returns
-//     x_new.  (The paper's test f/f' < 2 eps x is the special case of a
-//     vanishing step.)
+//   * the new iterate is the zero to relative precision 2 eps; returns it.
+//     The test is the paper's mean-value bound (x - zero < f(x)/f'(x) for x
+//     right of the zero) applied at x_new, with f(x_new) known in closed
+//     form: f - phi = -b2^2 ab (x - x_j)^3 / ((x_j + ab)^3 x (x + ab)), and
+//     phi(x_new) = 0, so f(x_new) = (w0 - 1) D^3 / (x_new (x_new + ab)),
+//     D = x - x_new; and f'(x_new) > f'(x) since f' decreases.  Hence
+//     x_new - zero < (w0 - 1) D^3 / (x_new (x_new + ab) f'(x)), a bound
+//     cubic in the step, checked without evaluating f at x_new.
 __device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop) {
   const Spec s = spec_eval(P, x);
   if (s.f <= 0.0) {
@@ -199,10 +215,11 @@ __device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop)
   // model phi = w0 x - sigma - w1/x matching f, f', f'' at x:
   // w0 = 1 + b2^2 ab / p^3; the increment D solves a D^2 + b D - f = 0 with
   // a = -w0/x and b = f' + f/x; D = 2f / (b + sqrt(b^2 + 4 a f)).
-  const double w0 = __builtin_fma(s.q2 * P.ab, s.rp * s.rp, 1.0);
+  const double w0m1 = (s.q2 * P.ab) * (s.rp * s.rp);
+  const double w0 = w0m1 + 1.0;
   const double a = -w0 * s.rx;
   const double b = __builtin_fma(s.f, s.rx, s.fp);
-  const double disc = __builtin_fmax(0.0, __builtin_fma(b, b, 4.0 * a * s.f));
+  const double disc = __builtin_fmax(0x1p-1000, __builtin_fma(b, b, 4.0 * a * s.f));
   // D to ~2^-46: an overshoot of the zero by the error of D, which cubic
   // convergence can leave within reach, must stay below the rounding level
   const double dl = (2.0 * s.f) * rcp1(b + sqrt1(disc));
@@ -222,7 +239,8 @@ __device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop)
     stop = true;
     return x;
   }
-  if (__builtin_fma(-(x - xn), s.fp, s.f) <= 2.0 * kEps64 * xn * s.fp) stop = true;
+  const double D = x - xn;
+  if (w0m1 * (D * D) * D <= 2.0 * kEps64 * (xn * xn) * (xn + P.ab) * s.fp) stop = true;
   return xn;
 }
 
@@ -252,8 +270,9 @@ __device__ __forceinline__ double newton_step(const Arrow1& P, double x, bool& s
 // so their latencies overlap; the loop runs until both have stopped.
 __device__ __forceinline__ void zeros_bg(const Arrow1& P1, const Arrow1& P2,
                                          double& x1, double& x2, int& it1, int& it2) {
-  x1 = bg_start(P1);
-  x2 = bg_start(P2);
+  const double rab = rcp1(P1.ab);  // both problems share abar
+  x1 = bg_start(P1, rab);
+  x2 = bg_start(P2, rab);
   bool s1 = false, s2 = false;
   it1 = 0;
   it2 = 0;
@@ -287,11 +306,18 @@ struct Arrow1f {
   float b1s, b2s, ab, gb;
 };
 
+__device__ __forceinline__ float quad_zero32(float c, float k) {
+  const float c2 = 0.5f * c;
+  const float s = __builtin_fabsf(c2) + __builtin_amdgcn_sqrtf(__builtin_fmaf(c2, c2, k));
+  return c >= 0.0f ? s : k * __builtin_amdgcn_rcpf(s);
+}
+
+// the same two upper bounds as bg_start
 __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
-  const float H = P.b1s + P.b2s;
-  const float g2 = 0.5f * P.gb;
-  const float disc = __builtin_amdgcn_sqrtf(__builtin_fmaf(g2, g2, H));
-  return P.gb >= 0.0f ? g2 + disc : H * __builtin_amdgcn_rcpf(disc - g2);
+  const float x_inf = quad_zero32(P.gb, P.b1s + P.b2s);
+  const float x_pole = quad_zero32(__builtin_fmaf(P.b2s, __builtin_amdgcn_rcpf(P.ab), P.gb),
+                                   P.b1s);
+  return __builtin_fminf(x_inf, x_pole);
 }
 
 __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop, bool& conv) {
@@ -307,7 +333,8 @@ __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop
     conv = true;
     return x;
   }
-  const float w0 = __builtin_fmaf(q2 * P.ab, rp * rp, 1.0f);
+  const float w0m1 = (q2 * P.ab) * (rp * rp);
+  const float w0 = w0m1 + 1.0f;
   const float a = -w0 * rx;
   const float b = __builtin_fmaf(f, rx, fp);
   const float disc = __builtin_fmaxf(0.0f, __builtin_fmaf(b, b, 4.0f * a * f));
@@ -328,7 +355,8 @@ __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop
     conv = true;
     return x;
   }
-  if (__builtin_fmaf(-(x - xn), fp, f) <= 4.0f * kEps32 * xn * fp) {
+  const float D = x - xn;
+  if (w0m1 * (D * D) * D <= 4.0f * kEps32 * (xn * xn) * (xn + P.ab) * fp) {
     stop = true;
     conv = true;
   }
@@ -516,28 +544,25 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
     }
   }
 
-  lam[0] = __builtin_amdgcn_ldexp(l0, e);
-  lam[1] = __builtin_amdgcn_ldexp(l1, e);
-  lam[2] = __builtin_amdgcn_ldexp(l2, e);
+  // a matrix with a non-finite entry was solved as zero; adding NaN marks
+  // every output (adding 0.0 elsewhere changes at most the sign of a zero)
+  const double poison = finite ? 0.0 : __builtin_nan("");
+  lam[0] = __builtin_amdgcn_ldexp(l0, e) + poison;
+  lam[1] = __builtin_amdgcn_ldexp(l1, e) + poison;
+  lam[2] = __builtin_amdgcn_ldexp(l2, e) + poison;
   if (VECS) {
     // back to A's coordinates: V = diag(J, 1) [v0 v1 v2]
-    V[0] = __builtin_fma(J.k11, v0.x, J.k12 * v0.y);
-    V[1] = __builtin_fma(J.k11, v1.x, J.k12 * v1.y);
-    V[2] = __builtin_fma(J.k11, v2.x, J.k12 * v2.y);
-    V[3] = __builtin_fma(J.k21, v0.x, J.k22 * v0.y);
-    V[4] = __builtin_fma(J.k21, v1.x, J.k22 * v1.y);
-    V[5] = __builtin_fma(J.k21, v2.x, J.k22 * v2.y);
-    V[6] = v0.z;
-    V[7] = v1.z;
-    V[8] = v2.z;
+    V[0] = __builtin_fma(J.k11, v0.x, __builtin_fma(J.k12, v0.y, poison));
+    V[1] = __builtin_fma(J.k11, v1.x, __builtin_fma(J.k12, v1.y, poison));
+    V[2] = __builtin_fma(J.k11, v2.x, __builtin_fma(J.k12, v2.y, poison));
+    V[3] = __builtin_fma(J.k21, v0.x, __builtin_fma(J.k22, v0.y, poison));
+    V[4] = __builtin_fma(J.k21, v1.x, __builtin_fma(J.k22, v1.y, poison));
+    V[5] = __builtin_fma(J.k21, v2.x, __builtin_fma(J.k22, v2.y, poison));
+    V[6] = v0.z + poison;
+    V[7] = v1.z + poison;
+    V[8] = v2.z + poison;
   }
   if (!finite) {
-    const double qnan = __builtin_nan("");
-    lam[0] = lam[1] = lam[2] = qnan;
-    if (VECS) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) V[k] = qnan;
-    }
     branch = kNonFinite;
   } else if (m == 0.0) {
     branch = kZero;

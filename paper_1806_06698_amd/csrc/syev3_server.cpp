@@ -103,11 +103,19 @@ struct Request {
   void* lam = nullptr;
   void* V = nullptr;
   hipEvent_t ready = nullptr;
+  // host staging (NULL when the request's data lives on the device)
+  const void* h_A = nullptr;
+  void* h_lam = nullptr;
+  void* h_V = nullptr;
   Clock::time_point t_submit, t_done;
 };
 
 struct TickSlot {
   hipStream_t stream = nullptr;
+  hipStream_t copy_in = nullptr;   // host-staged inputs
+  hipStream_t copy_out = nullptr;  // host-staged outputs
+  hipEvent_t in_done = nullptr;
+  hipEvent_t kernel_done = nullptr;
   hipEvent_t done = nullptr;
   syev3::TickTable* h_table = nullptr;  // pinned host
   syev3::TickTable* d_table = nullptr;  // device
@@ -173,6 +181,8 @@ int syev3_server::launch_tick(int slot) {
   syev3::TickTable* t = tk.h_table;
   int nseg = 0;
   int64_t tiles = 0;
+  bool staged_in = false, staged_out = false;
+  hipError_t e = hipSuccess;
   tk.reqs.clear();
   while (!queue.empty() && nseg < o.max_segments_per_tick) {
     const int ri = queue.front();
@@ -190,17 +200,45 @@ int syev3_server::launch_tick(int slot) {
     r.state = kRunning;
     tk.reqs.push_back(ri);
     if (r.ready) (void)hipStreamWaitEvent(tk.stream, r.ready, 0);
+    if (r.h_A && e == hipSuccess) {
+      const size_t es = r.dtype == SYEV3_F64 ? 8 : 4;
+      e = hipMemcpyAsync(r.A, r.h_A, 6 * (size_t)r.n * es, hipMemcpyHostToDevice, tk.copy_in);
+      staged_in = true;
+    }
+    if (r.h_lam) staged_out = true;
   }
   t->nseg = nseg;
   t->total_tiles = tiles;
-  hipError_t e;
-  if (tk.exec) {
-    e = hipGraphLaunch(tk.exec, tk.stream);
-  } else {
-    e = hipMemcpyAsync(tk.d_table, tk.h_table, table_bytes, hipMemcpyHostToDevice, tk.stream);
-    if (e == hipSuccess) e = syev3::launch_segments(tk.d_table, grid_blocks, tk.stream);
+  if (staged_in && e == hipSuccess) {
+    e = hipEventRecord(tk.in_done, tk.copy_in);
+    if (e == hipSuccess) e = hipStreamWaitEvent(tk.stream, tk.in_done, 0);
   }
-  if (e == hipSuccess) e = hipEventRecord(tk.done, tk.stream);
+  if (e == hipSuccess) {
+    if (tk.exec) {
+      e = hipGraphLaunch(tk.exec, tk.stream);
+    } else {
+      e = hipMemcpyAsync(tk.d_table, tk.h_table, table_bytes, hipMemcpyHostToDevice, tk.stream);
+      if (e == hipSuccess) e = syev3::launch_segments(tk.d_table, grid_blocks, tk.stream);
+    }
+  }
+  if (staged_out && e == hipSuccess) {
+    // results back on the copy-out stream; the tick completes after them
+    e = hipEventRecord(tk.kernel_done, tk.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(tk.copy_out, tk.kernel_done, 0);
+    for (int ri : tk.reqs) {
+      const Request& r = req[ri];
+      if (!r.h_lam || e != hipSuccess) continue;
+      const size_t es = r.dtype == SYEV3_F64 ? 8 : 4;
+      e = hipMemcpyAsync(r.h_lam, r.lam, 3 * (size_t)r.n * es, hipMemcpyDeviceToHost,
+                         tk.copy_out);
+      if (e == hipSuccess && r.h_V && r.vecs)
+        e = hipMemcpyAsync(r.h_V, r.V, 9 * (size_t)r.n * es, hipMemcpyDeviceToHost,
+                           tk.copy_out);
+    }
+    if (e == hipSuccess) e = hipEventRecord(tk.done, tk.copy_out);
+  } else if (e == hipSuccess) {
+    e = hipEventRecord(tk.done, tk.stream);
+  }
   if (e != hipSuccess) return SYEV3_E_HIP;
   tk.busy = true;
   if (busy_ticks++ == 0) busy_since = Clock::now();
@@ -301,6 +339,10 @@ int syev3_server_create(const syev3_server_opts* opts, syev3_server** out) {
   for (auto& tk : s->ticks) {
     if (rc != SYEV3_OK) break;
     if (hipStreamCreateWithFlags(&tk.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&tk.copy_in, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&tk.copy_out, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&tk.in_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&tk.kernel_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&tk.done, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void**)&tk.h_table, s->table_bytes, hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&tk.d_table, s->table_bytes) != hipSuccess) {
@@ -343,11 +385,17 @@ int syev3_server_destroy(syev3_server* s) {
   }
   for (auto& tk : s->ticks) {
     if (tk.stream) (void)hipStreamSynchronize(tk.stream);
+    if (tk.copy_in) (void)hipStreamSynchronize(tk.copy_in);
+    if (tk.copy_out) (void)hipStreamSynchronize(tk.copy_out);
     if (tk.exec) (void)hipGraphExecDestroy(tk.exec);
     if (tk.graph) (void)hipGraphDestroy(tk.graph);
     if (tk.d_table) (void)hipFree(tk.d_table);
     if (tk.h_table) (void)hipHostFree(tk.h_table);
     if (tk.done) (void)hipEventDestroy(tk.done);
+    if (tk.kernel_done) (void)hipEventDestroy(tk.kernel_done);
+    if (tk.in_done) (void)hipEventDestroy(tk.in_done);
+    if (tk.copy_out) (void)hipStreamDestroy(tk.copy_out);
+    if (tk.copy_in) (void)hipStreamDestroy(tk.copy_in);
     if (tk.stream) (void)hipStreamDestroy(tk.stream);
   }
   if (s->pool) (void)hipFree(s->pool);
@@ -386,6 +434,9 @@ int64_t syev3_server_acquire(syev3_server* s, int64_t n, int dtype, int want_vec
              : nullptr;
   r.ready = nullptr;
   r.failed = false;
+  r.h_A = nullptr;
+  r.h_lam = nullptr;
+  r.h_V = nullptr;
   s->st.pool_bytes_in_use = s->alloc->in_use();
   s->st.pool_bytes_peak = std::max<uint64_t>(s->st.pool_bytes_peak, s->alloc->in_use());
   bufs->A = r.A;
@@ -405,6 +456,28 @@ int syev3_server_submit(syev3_server* s, int64_t id, hipEvent_t ready) {
     if (!r || r->state != kAdmitted) return SYEV3_E_STATE;
     r->state = kQueued;
     r->ready = ready;
+    r->t_submit = Clock::now();
+    s->queue.push_back(slot);
+    s->st.submitted++;
+  }
+  s->cv_sched.notify_one();
+  return SYEV3_OK;
+}
+
+int syev3_server_submit_host(syev3_server* s, int64_t id, const void* host_A,
+                             void* host_lambda, void* host_V) {
+  if (!s) return SYEV3_E_STATE;
+  if (!host_A || !host_lambda) return SYEV3_E_NULL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    int slot;
+    Request* r = lookup(s, id, &slot);
+    if (!r || r->state != kAdmitted) return SYEV3_E_STATE;
+    r->state = kQueued;
+    r->ready = nullptr;
+    r->h_A = host_A;
+    r->h_lam = host_lambda;
+    r->h_V = r->vecs ? host_V : nullptr;
     r->t_submit = Clock::now();
     s->queue.push_back(slot);
     s->st.submitted++;
@@ -467,7 +540,8 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
   if (!s || !o || !out) return SYEV3_E_NULL;
   const bool closed = o->qps == 0.0;
   if (!(o->qps >= 0) || (closed && o->closed_concurrency < 1) || !(o->duration_s > 0) ||
-      o->src_n < 1 || !o->src_f64 || !o->src_f32 || !(o->max_log2_n >= 0))
+      o->src_n < 1 || !o->src_f64 || !o->src_f32 || !(o->max_log2_n >= 0) ||
+      (o->host_staged && (!o->sink || std::exp2(o->max_log2_n) > (double)o->src_n)))
     return SYEV3_E_N;
   std::memset(out, 0, sizeof(*out));
   hipStream_t prod = nullptr;
@@ -535,15 +609,24 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
       if (id < 0) { rc = (int)id; break; }
       const size_t es = a.dtype == SYEV3_F64 ? 8 : 4;
       const char* src = (const char*)(a.dtype == SYEV3_F64 ? o->src_f64 : o->src_f32);
-      const int64_t off = (int64_t)(U(rng) * (double)(o->src_n - a.n + 1));
       const int slot = (int)(id & 0xffffffff);
-      if (hipMemcpy2DAsync(b.A, (size_t)a.n * es, src + (size_t)off * es, (size_t)o->src_n * es,
-                           (size_t)a.n * es, 6, hipMemcpyDeviceToDevice, prod) != hipSuccess ||
-          hipEventRecord(ev[slot], prod) != hipSuccess) {
-        rc = SYEV3_E_HIP;
-        break;
+      if (o->host_staged) {
+        // the source pool holds 6 contiguous planes of max request size
+        char* sink = (char*)o->sink;
+        rc = syev3_server_submit_host(s, id, src, sink, o->want_vectors ? sink + 3 * (size_t)a.n * es
+                                                                          : nullptr);
+        if (rc != SYEV3_OK) break;
+      } else {
+        const int64_t off = (int64_t)(U(rng) * (double)(o->src_n - a.n + 1));
+        if (hipMemcpy2DAsync(b.A, (size_t)a.n * es, src + (size_t)off * es,
+                             (size_t)o->src_n * es, (size_t)a.n * es, 6,
+                             hipMemcpyDeviceToDevice, prod) != hipSuccess ||
+            hipEventRecord(ev[slot], prod) != hipSuccess) {
+          rc = SYEV3_E_HIP;
+          break;
+        }
+        if ((rc = syev3_server_submit(s, id, ev[slot])) != SYEV3_OK) break;
       }
-      if ((rc = syev3_server_submit(s, id, ev[slot])) != SYEV3_OK) break;
       admit_wait_sum += seconds_since(t0, Clock::now()) - a.t;
       admitted++;
       live.push_back(Live{id, a.t, a.n});

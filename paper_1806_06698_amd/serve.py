@@ -17,7 +17,8 @@ class LoadgenOpts(ctypes.Structure):
                 ("max_log2_n", ctypes.c_double), ("frac_f32", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("src_f64", ctypes.c_void_p),
                 ("src_f32", ctypes.c_void_p), ("src_n", ctypes.c_int64),
-                ("want_vectors", ctypes.c_int32)]
+                ("want_vectors", ctypes.c_int32), ("host_staged", ctypes.c_int32),
+                ("sink", ctypes.c_void_p)]
 
 
 class LoadgenResult(ctypes.Structure):
@@ -39,6 +40,9 @@ def _bind(L):
     L.syev3_server_loadgen.argtypes = [ctypes.c_void_p, ctypes.POINTER(LoadgenOpts),
                                        ctypes.POINTER(LoadgenResult)]
     L.syev3_server_loadgen.restype = ctypes.c_int
+    L.syev3_server_submit_host.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]
+    L.syev3_server_submit_host.restype = ctypes.c_int
     L._serve_bound = True
     return L
 
@@ -110,6 +114,17 @@ class Server:
         ev = ctypes.c_void_p(ready_event.cuda_event if ready_event is not None else 0)
         _lib.check(self.L.syev3_server_submit(self.h, req.id, ev), "syev3_server_submit")
 
+    def submit_host(self, req: Request, host_A, host_lam, host_V=None):
+        """Host-staged submission: host_A (6, n), host_lam (3, n), host_V
+        (9, n) are CPU tensors of the request's dtype, preferably pinned; the
+        server copies A in before the tick and the results out after it."""
+        for t in (host_A, host_lam) + ((host_V,) if host_V is not None else ()):
+            if t.is_cuda or not t.is_contiguous():
+                raise ValueError("host buffers must be contiguous CPU tensors")
+        _lib.check(self.L.syev3_server_submit_host(
+            self.h, req.id, host_A.data_ptr(), host_lam.data_ptr(),
+            host_V.data_ptr() if host_V is not None else None), "syev3_server_submit_host")
+
     def poll(self, req):
         lat = ctypes.c_double()
         rc = _lib.check(self.L.syev3_server_poll(self.h, req.id, ctypes.byref(lat)),
@@ -131,14 +146,20 @@ class Server:
         return {f: getattr(s, f) for f, _ in s._fields_}
 
     def loadgen(self, src_f64, src_f32, qps, duration_s, max_log2_n=20.0,
-                frac_f32=0.5, seed=0, vectors=True, concurrency=0) -> dict:
+                frac_f32=0.5, seed=0, vectors=True, concurrency=0, sink=None) -> dict:
         """qps > 0: open-loop Poisson arrivals; qps == 0: closed loop with
-        `concurrency` requests in flight."""
+        `concurrency` requests in flight.  Sources on the device: inputs are
+        copied on the device.  Sources in (pinned) host memory together with a
+        host `sink`: host-staged requests."""
+        staged = not src_f64.is_cuda
+        if staged and sink is None:
+            raise ValueError("host-staged load needs a pinned host sink")
         o = LoadgenOpts(qps=qps, closed_concurrency=concurrency,
                         duration_s=duration_s, max_log2_n=max_log2_n,
                         frac_f32=frac_f32, seed=seed, src_f64=src_f64.data_ptr(),
-                        src_f32=src_f32.data_ptr(), src_n=src_f64.shape[1],
-                        want_vectors=1 if vectors else 0)
+                        src_f32=src_f32.data_ptr(), src_n=src_f64.shape[-1],
+                        want_vectors=1 if vectors else 0, host_staged=1 if staged else 0,
+                        sink=sink.data_ptr() if sink is not None else None)
         r = LoadgenResult()
         _lib.check(self.L.syev3_server_loadgen(self.h, ctypes.byref(o), ctypes.byref(r)),
                    "syev3_server_loadgen")
@@ -169,5 +190,13 @@ def bench(duration_s=4.0, budget_bytes=64 << 30, seed=3):
             r = srv.loadgen(A, Af, qps=rho * rate, duration_s=duration_s, seed=seed + 1)
             r["offered_qps"] = rho * rate
             out[f"open_loop_{int(rho * 100)}pct"] = r
+        # host-staged: inputs from pinned host memory, results back to it
+        m = 1 << 20
+        hA = A[:, :m].cpu().contiguous().pin_memory()
+        hAf = Af[:, :m].cpu().contiguous().pin_memory()
+        sink = torch.empty(12 * m, dtype=torch.float64).pin_memory()
+        r = srv.loadgen(hA, hAf, qps=0.0, concurrency=64, duration_s=min(2.0, duration_s),
+                        seed=seed + 2, sink=sink)
+        out["host_staged_closed_loop_64_in_flight"] = r
         out["server_stats"] = srv.stats()
     return out

@@ -147,3 +147,38 @@ def test_loadgen_short_run(source):
     assert res["requests"] > 100
     assert 0 < res["lat_p50_s"] <= res["lat_p99_s"] <= res["lat_max_s"]
     assert res["matrices"] > 0 and res["ticks"] > 0
+
+
+def test_host_staged_requests_match_the_device_path(source):
+    A64, A32 = source
+    with serve.Server(hbm_budget_bytes=1 << 30, max_inflight_ticks=3) as srv:
+        reqs = []
+        for k, n in enumerate([1, 300, 4097, 70_000, 200_001]):
+            dt = s3.F64 if k % 2 == 0 else s3.F32_REFINE
+            src = (A64 if dt == s3.F64 else A32)[:, 1000:1000 + n]
+            tdt = torch.float64 if dt == s3.F64 else torch.float32
+            hA = src.cpu().contiguous().pin_memory()
+            hl = torch.empty((3, n), dtype=tdt).pin_memory()
+            hV = torch.empty((9, n), dtype=tdt).pin_memory()
+            r = srv.acquire(n, dt)
+            srv.submit_host(r, hA, hl, hV)
+            reqs.append((r, src.contiguous(), hl, hV))
+        for r, src, hl, hV in reqs:
+            srv.wait(r, timeout_s=60.0)
+            lam, V = s3.syev3(src)
+            torch.cuda.synchronize()
+            assert torch.equal(lam.cpu(), hl) and torch.equal(V.cpu(), hV)
+            srv.release(r)
+
+
+def test_host_staged_loadgen(source):
+    A64, A32 = source
+    m = 1 << 16
+    hA = A64[:, :m].cpu().contiguous().pin_memory()
+    hAf = A32[:, :m].cpu().contiguous().pin_memory()
+    sink = torch.empty(12 * m, dtype=torch.float64).pin_memory()
+    with serve.Server(hbm_budget_bytes=1 << 30) as srv:
+        res = srv.loadgen(hA, hAf, qps=0.0, concurrency=16, duration_s=0.5,
+                          max_log2_n=16, seed=9, sink=sink)
+    print(res, flush=True)
+    assert res["requests"] > 10 and res["lat_p99_s"] > 0
