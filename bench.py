@@ -14,6 +14,7 @@ the stress mix, the 2^28 wide-range batch, serving) go into the same line.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import math
@@ -181,6 +182,20 @@ def main():
 
     total_s, per_ms, span_s = timed_launches(step, args.steps, args.warmup, torch)
     ms_launch = sum(per_ms) / len(per_ms)
+
+    # the same loads and stores with the solve taken out: the practical HBM
+    # ceiling of this traffic on this device
+    from paper_1806_06698_amd import _lib
+    sh = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def stream_ref():
+        rc = _lib.lib().syev3_stream_reference(n, ctypes.c_void_p(A.data_ptr()),
+                                               ctypes.c_void_p(lam.data_ptr()),
+                                               ctypes.c_void_p(V.data_ptr()), 0, sh)
+        _lib.check(rc, "syev3_stream_reference")
+
+    _, ref_ms, _ = timed_launches(stream_ref, max(5, args.steps // 2), 2, torch)
+    ms_ref = sum(ref_ms) / len(ref_ms)
     ms_per_step = span_s * 1e3 / args.steps
     value = n * args.steps / span_s
     bytes_launch = BYTES_PER_MATRIX[("f64", True)] * n
@@ -207,7 +222,9 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_syev3_soa<double, vecs>",
                      "algorithmic_bytes_per_launch": bytes_launch,
-                     "ms_per_launch": ms_launch},
+                     "ms_per_launch": ms_launch,
+                     "stream_ceiling_GBps": bytes_launch / (ms_ref * 1e-3) / 1e9,
+                     "frac_of_stream_ceiling": ms_ref / ms_launch},
         "kernel_hash": khash,
     }
     del A, lam, V

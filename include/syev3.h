@@ -135,6 +135,16 @@ int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
                        void* lambda, void* V, int dtype, uint32_t flags,
                        int32_t* info, hipStream_t stream);
 
+/*
+ * syev3_stream_reference -- measurement aid, not a solver: reads the 6
+ * input planes and writes the 3 + 9 output planes (V may be NULL) exactly
+ * as batched_syev3 does in SoA layout with ld = n, with trivial arithmetic
+ * in between.  Its bandwidth is the practical HBM ceiling of the solver's
+ * memory traffic on the device.  Same argument rules as batched_syev3.
+ */
+int syev3_stream_reference(int64_t n, const void* A_upper6, void* lambda, void* V,
+                           int dtype, hipStream_t stream);
+
 /* Text for an error code (static storage). */
 const char* syev3_strerror(int code);
 

@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
     L.batched_syev3_inplace.restype = i32
     L.batched_syev3_info.argtypes = [i64, vp, i64, i32, vp, vp, i32, u32, vp, vp]
     L.batched_syev3_info.restype = i32
+    L.syev3_stream_reference.argtypes = [i64, vp, vp, vp, i32, vp]
+    L.syev3_stream_reference.restype = i32
     L.syev3_strerror.argtypes = [i32]
     L.syev3_strerror.restype = ctypes.c_char_p
     L.syev3_version.argtypes = []

@@ -100,6 +100,15 @@ int batched_syev3_inplace(int64_t n, void* A, void* lambda, int dtype,
   return batched_syev3_info(n, A, 0, SYEV3_AOS9, lambda, A, dtype, 0u, nullptr, stream);
 }
 
+int syev3_stream_reference(int64_t n, const void* A, void* lambda, void* V, int dtype,
+                           hipStream_t stream) {
+  int64_t ld = 0;
+  const int rc = check_args(n, A, ld, SYEV3_SOA, lambda, V, dtype, 0u);
+  if (rc != SYEV3_OK || n == 0) return rc;
+  const hipError_t e = syev3::launch_stream_reference(n, A, lambda, V, dtype, stream);
+  return e == hipSuccess ? SYEV3_OK : SYEV3_E_HIP;
+}
+
 const char* syev3_strerror(int code) {
   switch (code) {
     case SYEV3_OK: return "success";

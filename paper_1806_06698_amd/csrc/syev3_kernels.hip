@@ -186,6 +186,44 @@ hipError_t launch_segments(const TickTable* table, int32_t grid_blocks,
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Streaming reference: the SoA kernel's loads and stores, with a sum in
+// place of the solve.
+// ---------------------------------------------------------------------------
+template <typename T, bool VECS>
+__global__ __launch_bounds__(kBlock) void k_stream_reference(int64_t n, const T* __restrict__ A,
+                                                             T* __restrict__ lam,
+                                                             T* __restrict__ V) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s += ld_stream(A + k * n + i);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) st_stream(s * (T)(j + 1), lam + j * n + i);
+  if (VECS) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) st_stream(s * (T)(k + 4), V + k * n + i);
+  }
+}
+
+hipError_t launch_stream_reference(int64_t n, const void* A, void* lambda, void* V,
+                                   int dtype, hipStream_t stream) {
+  const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+  if (dtype == 0) {
+    if (V) hipLaunchKernelGGL((k_stream_reference<double, true>), grid, block, 0, stream, n,
+                              (const double*)A, (double*)lambda, (double*)V);
+    else hipLaunchKernelGGL((k_stream_reference<double, false>), grid, block, 0, stream, n,
+                            (const double*)A, (double*)lambda, (double*)V);
+  } else {
+    if (V) hipLaunchKernelGGL((k_stream_reference<float, true>), grid, block, 0, stream, n,
+                              (const float*)A, (float*)lambda, (float*)V);
+    else hipLaunchKernelGGL((k_stream_reference<float, false>), grid, block, 0, stream, n,
+                            (const float*)A, (float*)lambda, (float*)V);
+  }
+  return hipGetLastError();
+}
+
 int device_cu_count() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;

@@ -170,26 +170,37 @@ __device__ __forceinline__ Spec spec_eval(const Arrow1& P, double x) {
   return s;
 }
 
-// Starting point: the smaller of two upper bounds of the zero.
+// Starting point: upper bounds of the zero, each the positive zero of a
+// quadratic that lies below f on an interval containing the zero (f is
+// increasing, so that quadratic's zero is right of f's).
 //  * x_inf, the zero of x - gb - (b1^2 + b2^2)/x: the first iterate from
-//    +infinity (Sec. 1.4.1); f exceeds that function on (0, inf) because
-//    1/(x + ab) < 1/x.  Tight when ab is small against the zero.
-//  * x_pole, the zero of x - gb - b1^2/x - b2^2/ab: f exceeds it because
-//    1/(x + ab) < 1/ab.  Tight when the zero is small against ab (a zero next
-//    to the pole at 0), where x_inf can be off by many orders of magnitude.
-// Both are positive zeros of x^2 - c x - k, taken in the form without
-// cancellation.  rab = 1/ab.  An iterate that rounding puts left of the zero
-// is caught by the step (f <= 0).
-__device__ __forceinline__ double quad_zero(double c, double k) {
+//    +infinity (Sec. 1.4.1); below f because 1/(x + ab) < 1/x.  Tight when
+//    ab is small against the zero.
+//  * x_pole, the zero of x - gb - b1^2/x - b2^2/ab: below f because
+//    1/(x + ab) < 1/ab.  Tight when the zero is small against ab (next to
+//    the pole at 0), where x_inf can be off by orders of magnitude.
+//  * U = min(x_inf, x_pole); then x_chord, the zero of the same function
+//    with 1/(x + ab) replaced by its chord over [0, U], which lies above it
+//    there (convexity), so below f on (0, U].  x_chord is in [zero, U].
+// An iterate that rounding puts left of the zero is caught by the step
+// (f <= 0).  rab = 1/ab.
+// quad_zero(c, k, a): positive zero of a x^2 - c x - k (a, k > 0), in the
+// form without cancellation.
+__device__ __forceinline__ double quad_zero(double c, double k, double a) {
   const double c2 = 0.5 * c;
-  const double s = dabs(c2) + sqrt1(__builtin_fma(c2, c2, k));
-  return c >= 0.0 ? s : k * rcp1(s);
+  const double s = dabs(c2) + sqrt1(__builtin_fma(c2, c2, a * k));
+  const bool pos = c >= 0.0;
+  return (pos ? s : k) * rcp1(pos ? a : s);
 }
 
 __device__ __forceinline__ double bg_start(const Arrow1& P, double rab) {
-  const double x_inf = quad_zero(P.gb, P.b1s + P.b2s);
-  const double x_pole = quad_zero(__builtin_fma(P.b2s, rab, P.gb), P.b1s);
-  return __builtin_fmin(x_inf, x_pole);
+  const double x_inf = quad_zero(P.gb, P.b1s + P.b2s, 1.0);
+  const double b2r = P.b2s * rab;
+  const double c = P.gb + b2r;
+  const double U = __builtin_fmin(x_inf, quad_zero(c, P.b1s, 1.0));
+  // chord of 1/(x + ab) over [0, U]: 1/ab - x / (ab (U + ab))
+  const double k = b2r * rcp1(U + P.ab);
+  return __builtin_fmin(U, quad_zero(c, P.b1s, 1.0 + k));
 }
 
 // One Borges-Gragg step from x (to the right of the zero).  Sets stop when
@@ -306,18 +317,21 @@ struct Arrow1f {
   float b1s, b2s, ab, gb;
 };
 
-__device__ __forceinline__ float quad_zero32(float c, float k) {
+__device__ __forceinline__ float quad_zero32(float c, float k, float a) {
   const float c2 = 0.5f * c;
-  const float s = __builtin_fabsf(c2) + __builtin_amdgcn_sqrtf(__builtin_fmaf(c2, c2, k));
-  return c >= 0.0f ? s : k * __builtin_amdgcn_rcpf(s);
+  const float s = __builtin_fabsf(c2) + __builtin_amdgcn_sqrtf(__builtin_fmaf(c2, c2, a * k));
+  const bool pos = c >= 0.0f;
+  return (pos ? s : k) * __builtin_amdgcn_rcpf(pos ? a : s);
 }
 
-// the same two upper bounds as bg_start
+// the same upper bounds as bg_start
 __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
-  const float x_inf = quad_zero32(P.gb, P.b1s + P.b2s);
-  const float x_pole = quad_zero32(__builtin_fmaf(P.b2s, __builtin_amdgcn_rcpf(P.ab), P.gb),
-                                   P.b1s);
-  return __builtin_fminf(x_inf, x_pole);
+  const float x_inf = quad_zero32(P.gb, P.b1s + P.b2s, 1.0f);
+  const float b2r = P.b2s * __builtin_amdgcn_rcpf(P.ab);
+  const float c = P.gb + b2r;
+  const float U = __builtin_fminf(x_inf, quad_zero32(c, P.b1s, 1.0f));
+  const float k = b2r * __builtin_amdgcn_rcpf(U + P.ab);
+  return __builtin_fminf(U, quad_zero32(c, P.b1s, 1.0f + k));
 }
 
 __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop, bool& conv) {

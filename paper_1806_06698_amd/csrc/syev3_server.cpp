@@ -145,6 +145,9 @@ struct syev3_server {
   std::thread thr;
 
   syev3_server_stats st{};
+  // completion list for the built-in load generator (off otherwise)
+  bool track_done = false;
+  std::vector<int64_t> done_ids;
   int busy_ticks = 0;
   Clock::time_point busy_since;
   Clock::time_point t0 = Clock::now();
@@ -266,6 +269,7 @@ void syev3_server::scheduler() {
         r.t_done = now;
         st.completed++;
         st.matrices_completed += r.n;
+        if (track_done) done_ids.push_back(make_id(ri, r.gen));
       }
       tk.reqs.clear();
       tk.busy = false;
@@ -282,6 +286,7 @@ void syev3_server::scheduler() {
             req[ri].state = kDone;
             req[ri].failed = true;
             req[ri].t_done = now;
+            if (track_done) done_ids.push_back(make_id(ri, req[ri].gen));
           }
           ticks[k].reqs.clear();
           any_done = true;
@@ -291,8 +296,11 @@ void syev3_server::scheduler() {
     if (any_done) cv_done.notify_all();
     if (stop && busy_ticks == 0 && queue.empty()) break;
     if (busy_ticks > 0) {
-      // poll completions at a short period while work is on the device
-      cv_sched.wait_for(lk, std::chrono::microseconds(20));
+      // poll completions while work is on the device (the scheduler keeps
+      // one host core busy then; it sleeps when the device is idle)
+      lk.unlock();
+      std::this_thread::yield();
+      lk.lock();
     } else {
       cv_sched.wait(lk, [&] { return stop || !queue.empty(); });
     }
@@ -546,15 +554,6 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
   std::memset(out, 0, sizeof(*out));
   hipStream_t prod = nullptr;
   if (hipStreamCreateWithFlags(&prod, hipStreamNonBlocking) != hipSuccess) return SYEV3_E_HIP;
-  const int nslots = s->o.max_requests;
-  std::vector<hipEvent_t> ev(nslots, nullptr);
-  for (auto& e : ev) {
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      for (auto& f : ev) if (f) (void)hipEventDestroy(f);
-      (void)hipStreamDestroy(prod);
-      return SYEV3_E_HIP;
-    }
-  }
   std::mt19937_64 rng(o->seed);
   std::uniform_real_distribution<double> U(0.0, 1.0);
   std::exponential_distribution<double> gap(closed ? 1.0 : o->qps);
@@ -564,17 +563,22 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
     int dtype;
   };
   struct Live {
-    int64_t id;
     double t_arrival;
     int64_t n;
   };
   std::deque<Arrival> waiting;
-  std::vector<Live> live;
+  std::map<int64_t, Live> live;
   std::vector<double> lat;
+  std::vector<int64_t> batch, done;
   double admit_wait_sum = 0.0;
   int64_t admitted = 0;
   syev3_server_stats st0{};
   syev3_server_get_stats(s, &st0);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->track_done = true;
+    s->done_ids.clear();
+  }
   const auto t0 = Clock::now();
   double next_t = closed ? 0.0 : gap(rng);
   double last_done = 0.0;
@@ -582,8 +586,8 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
   auto draw = [&](double t) {
     Arrival a;
     a.t = t;
-    a.n = std::max<int64_t>(1, std::min<int64_t>(o->src_n,
-                                                 (int64_t)std::floor(std::exp2(U(rng) * o->max_log2_n))));
+    a.n = std::max<int64_t>(
+        1, std::min<int64_t>(o->src_n, (int64_t)std::floor(std::exp2(U(rng) * o->max_log2_n))));
     a.dtype = U(rng) < o->frac_f32 ? SYEV3_F32_REFINE : SYEV3_F64;
     return a;
   };
@@ -600,7 +604,9 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
         next_t += gap(rng);
       }
     }
-    // admit in arrival order
+    // admit in arrival order; write the inputs of the whole batch, then
+    // submit it at once
+    batch.clear();
     while (!waiting.empty()) {
       const Arrival& a = waiting.front();
       syev3_request_buffers b;
@@ -609,67 +615,93 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
       if (id < 0) { rc = (int)id; break; }
       const size_t es = a.dtype == SYEV3_F64 ? 8 : 4;
       const char* src = (const char*)(a.dtype == SYEV3_F64 ? o->src_f64 : o->src_f32);
-      const int slot = (int)(id & 0xffffffff);
       if (o->host_staged) {
-        // the source pool holds 6 contiguous planes of max request size
+        // the request's input is the first 6 n values of the host source;
+        // every request's results land in the same host sink
         char* sink = (char*)o->sink;
-        rc = syev3_server_submit_host(s, id, src, sink, o->want_vectors ? sink + 3 * (size_t)a.n * es
-                                                                          : nullptr);
+        rc = syev3_server_submit_host(s, id, src, sink,
+                                      o->want_vectors ? sink + 3 * (size_t)a.n * es : nullptr);
         if (rc != SYEV3_OK) break;
       } else {
         const int64_t off = (int64_t)(U(rng) * (double)(o->src_n - a.n + 1));
         if (hipMemcpy2DAsync(b.A, (size_t)a.n * es, src + (size_t)off * es,
                              (size_t)o->src_n * es, (size_t)a.n * es, 6,
-                             hipMemcpyDeviceToDevice, prod) != hipSuccess ||
-            hipEventRecord(ev[slot], prod) != hipSuccess) {
+                             hipMemcpyDeviceToDevice, prod) != hipSuccess) {
           rc = SYEV3_E_HIP;
           break;
         }
-        if ((rc = syev3_server_submit(s, id, ev[slot])) != SYEV3_OK) break;
+        batch.push_back(id);
       }
       admit_wait_sum += seconds_since(t0, Clock::now()) - a.t;
       admitted++;
-      live.push_back(Live{id, a.t, a.n});
+      live[id] = Live{a.t, a.n};
       waiting.pop_front();
+    }
+    if (rc == SYEV3_OK && !batch.empty()) {
+      if (hipStreamSynchronize(prod) != hipSuccess) {
+        rc = SYEV3_E_HIP;
+      } else {
+        {
+          std::lock_guard<std::mutex> lk(s->mu);
+          const auto ts = Clock::now();
+          for (int64_t id : batch) {
+            int slot;
+            Request* r = lookup(s, id, &slot);
+            if (!r || r->state != kAdmitted) { rc = SYEV3_E_STATE; break; }
+            r->state = kQueued;
+            r->ready = nullptr;
+            r->t_submit = ts;
+            s->queue.push_back(slot);
+            s->st.submitted++;
+          }
+        }
+        s->cv_sched.notify_one();
+      }
     }
     if (rc != SYEV3_OK) break;
     // completions
-    for (size_t k = 0; k < live.size();) {
-      double l;
-      const int p = syev3_server_poll(s, live[k].id, &l);
-      if (p == 1) {
-        const double tnow = seconds_since(t0, Clock::now());
-        lat.push_back(tnow - live[k].t_arrival);
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      done.swap(s->done_ids);
+      s->done_ids.clear();
+    }
+    if (!done.empty()) {
+      const double tnow = seconds_since(t0, Clock::now());
+      for (int64_t id : done) {
+        auto it = live.find(id);
+        if (it == live.end()) continue;
+        lat.push_back(tnow - it->second.t_arrival);
         last_done = tnow;
-        out->matrices += live[k].n;
+        out->matrices += it->second.n;
         out->requests++;
-        syev3_server_release(s, live[k].id);
-        live[k] = live.back();
-        live.pop_back();
-      } else if (p < 0) {
-        rc = p;
-        break;
-      } else {
-        ++k;
+        const int p = syev3_server_release(s, id);
+        if (p < 0 && rc == SYEV3_OK) rc = p;
+        live.erase(it);
       }
+      done.clear();
     }
     if (rc != SYEV3_OK) break;
     if (next_t >= o->duration_s && waiting.empty() && live.empty()) break;
     std::this_thread::yield();
   }
   // drain whatever is still live after an error
-  for (auto& lv : live) {
-    (void)syev3_server_wait(s, lv.id, 10.0, nullptr);
-    (void)syev3_server_release(s, lv.id);
+  for (auto& kv : live) {
+    (void)syev3_server_wait(s, kv.first, 10.0, nullptr);
+    (void)syev3_server_release(s, kv.first);
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->track_done = false;
+    s->done_ids.clear();
   }
   (void)hipStreamSynchronize(prod);
-  for (auto& e : ev) (void)hipEventDestroy(e);
   (void)hipStreamDestroy(prod);
   if (rc != SYEV3_OK) return rc;
   std::sort(lat.begin(), lat.end());
   auto pct = [&](double q) {
     if (lat.empty()) return 0.0;
-    const size_t i = std::min(lat.size() - 1, (size_t)std::floor(q * (double)(lat.size() - 1) + 0.5));
+    const size_t i =
+        std::min(lat.size() - 1, (size_t)std::floor(q * (double)(lat.size() - 1) + 0.5));
     return lat[i];
   };
   double sum = 0.0;
