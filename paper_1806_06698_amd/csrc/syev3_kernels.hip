@@ -47,6 +47,38 @@ __global__ __launch_bounds__(kBlock) void k_syev3_soa(
   if (INFO) info[i] = code;
 }
 
+// The same with the 18 plane base addresses passed as kernel arguments
+// (uniform, held in scalar registers) and a 32-bit byte offset per lane, for
+// n * sizeof(T) < 2^32: loads and stores take the scalar-base addressing form
+// and need no 64-bit address arithmetic per lane.
+template <typename T>
+struct Planes {
+  const T* a[6];
+  T* l[3];
+  T* v[9];
+};
+
+template <typename T, bool VECS, bool INFO>
+__global__ __launch_bounds__(kBlock) void k_syev3_soa32(uint32_t n, Planes<T> P, uint32_t flags,
+                                                       int32_t* __restrict__ info) {
+  const uint32_t i = blockIdx.x * (uint32_t)kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t off = i * (uint32_t)sizeof(T);  // byte offset within a plane
+  double a[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    a[k] = (double)ld_stream((const T*)((const char*)P.a[k] + off));
+  double l[3], v[9];
+  const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) st_stream((T)l[j], (T*)((char*)P.l[j] + off));
+  if (VECS) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) st_stream((T)v[k], (T*)((char*)P.v[k] + off));
+  }
+  if (INFO) info[i] = code;
+}
+
 // AoS: IN = 6 (unique entries) or 9 (full row-major matrix, upper triangle
 // read).  The whole block is read into LDS before any global store, so the
 // full-matrix input may be overwritten by V (in place).  A is therefore not
@@ -99,7 +131,14 @@ static hipError_t launch_t(int64_t n, const void* A, int64_t ld, int layout,
                            hipStream_t stream) {
   const int64_t blocks = (n + kBlock - 1) / kBlock;
   const dim3 grid((unsigned)blocks), block(kBlock);
-  if (layout == 0) {
+  if (layout == 0 && (uint64_t)n * sizeof(T) <= (uint64_t)UINT32_MAX) {
+    Planes<T> P;
+    for (int k = 0; k < 6; ++k) P.a[k] = (const T*)A + k * ld;
+    for (int j = 0; j < 3; ++j) P.l[j] = (T*)lambda + j * ld;
+    for (int k = 0; k < 9; ++k) P.v[k] = VECS ? (T*)V + k * ld : nullptr;
+    hipLaunchKernelGGL((k_syev3_soa32<T, VECS, INFO>), grid, block, 0, stream, (uint32_t)n, P,
+                       flags, info);
+  } else if (layout == 0) {
     hipLaunchKernelGGL((k_syev3_soa<T, VECS, INFO>), grid, block, 0, stream, n, ld,
                        (const T*)A, (T*)lambda, (T*)V, flags, info);
   } else if (layout == 1) {

@@ -555,15 +555,18 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
       const double mua = mu + al, nua = nu + al;
       const Vec3 u1{be1 * mua, be2 * mu, mu * mua};
       const Vec3 u3{be1 * nu, be2 * nua, -nu * nua};
-      const Vec3 u2{-be2 * mu * nua, be1 * nu * mua, be1 * be2 * al};
       v2 = normalized(u1);
       v0 = normalized(u3);
-      v1 = normalized(u2);
       if (F32R) {
-        // one modified Gram-Schmidt pass over (u1, u3, u2)
+        // one Gram-Schmidt re-orthogonalisation: u3 against u1, then the
+        // middle vector as their cross product (the paper's u2 is u1 x u3
+        // up to a positive factor), orthogonal to both by construction
         v0 = normalized(axpy(-dot(v2, v0), v2, v0));
-        v1 = axpy(-dot(v2, v1), v2, v1);
-        v1 = normalized(axpy(-dot(v0, v1), v0, v1));
+        v1 = Vec3{__builtin_fma(v2.y, v0.z, -v2.z * v0.y), __builtin_fma(v2.z, v0.x, -v2.x * v0.z),
+                  __builtin_fma(v2.x, v0.y, -v2.y * v0.x)};
+      } else {
+        const Vec3 u2{-be2 * mu * nua, be1 * nu * mua, be1 * be2 * al};
+        v1 = normalized(u2);
       }
     }
   }
