@@ -220,7 +220,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_syev3_soa<double, vecs>",
+                     "kernel": "k_syev3_soa32<double, vecs>",
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "ms_per_launch": ms_launch,
                      "stream_ceiling_GBps": bytes_launch / (ms_ref * 1e-3) / 1e9,
