@@ -33,6 +33,7 @@
 
 #include "syev3.h"
 #include "syev3_internal.hpp"
+#include "syev3_pool.hpp"
 
 namespace {
 
@@ -45,49 +46,6 @@ double seconds_since(Clock::time_point t0, Clock::time_point t) {
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// First-fit allocator over [0, size) with coalescing frees.
-class PoolAllocator {
- public:
-  explicit PoolAllocator(size_t size) : size_(size) { free_[0] = size; }
-  bool alloc(size_t bytes, size_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rest = it->second - bytes;
-        const size_t noff = it->first + bytes;
-        free_.erase(it);
-        if (rest) free_[noff] = rest;
-        in_use_ += bytes;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    in_use_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t in_use() const { return in_use_; }
-  size_t size() const { return size_; }
-
- private:
-  size_t size_;
-  size_t in_use_ = 0;
-  std::map<size_t, size_t> free_;
-};
 
 enum ReqState { kFree = 0, kAdmitted, kQueued, kRunning, kDone };
 
@@ -131,7 +89,7 @@ struct syev3_server {
   syev3_server_opts o{};
   int device = 0;
   char* pool = nullptr;
-  PoolAllocator* alloc = nullptr;
+  syev3::PoolAllocator* alloc = nullptr;
   std::vector<Request> req;
   std::vector<int> free_slots;
   std::deque<int> queue;
@@ -338,7 +296,7 @@ int syev3_server_create(const syev3_server_opts* opts, syev3_server** out) {
     s->pool = nullptr;
     rc = SYEV3_E_BUDGET;
   }
-  s->alloc = new PoolAllocator(o.hbm_budget_bytes);
+  s->alloc = new syev3::PoolAllocator(o.hbm_budget_bytes);
   s->req.resize(o.max_requests);
   for (int k = o.max_requests - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->table_bytes = syev3::tick_table_bytes(o.max_segments_per_tick);
