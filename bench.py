@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector, vendor figure
 BYTES_PER_MATRIX = {  # algorithmic: 6 entries in, 3 (+9) out
     ("f64", True): 144, ("f64", False): 72, ("f32r", True): 72, ("f32r", False): 36,
+    ("f32", True): 72, ("f32", False): 36,
 }
 KERNEL_SOURCES = ["paper_1806_06698_amd/csrc/syev3_lane.hpp",
                   "paper_1806_06698_amd/csrc/syev3_kernels.hip"]
@@ -128,15 +129,15 @@ def cpu_baseline(torch, gen, target_s):
                       f"threads"}
 
 
-def f32r_errors(torch, gen, s3, n_sample=200_000):
-    """Per-result error of the FP32-storage form against the FP64 oracle on
+def f32r_errors(torch, gen, s3, n_sample=200_000, refine=True):
+    """Per-result error of an FP32-storage form against the FP64 oracle on
     a sample of the SPD workload (the FP32 inputs, exactly widened)."""
     import numpy as np
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import checks
     A = gen.spd_fe(n_sample, seed=2, device="cuda").float()
-    lam, V = s3.syev3(A)
+    lam, V = s3.syev3(A, refine=refine)
     torch.cuda.synchronize()
     A6 = A.t().double().cpu().numpy()
     lam_o, _ = oracle.solve(A6)
@@ -235,9 +236,10 @@ def main():
 
         def run_variant(name, A, layout, vectors, dtype_key, steps=10):
             nn = A.shape[1] if layout == "soa" else A.shape[0]
-            out = s3.syev3(A, layout=layout, vectors=vectors)
+            refine = dtype_key != "f32"
+            out = s3.syev3(A, layout=layout, vectors=vectors, refine=refine)
             torch.cuda.synchronize()
-            fn = (lambda: s3.syev3(A, layout=layout, vectors=vectors, out=out))
+            fn = (lambda: s3.syev3(A, layout=layout, vectors=vectors, out=out, refine=refine))
             _, per, span = timed_launches(fn, steps, 2, torch)
             msl = sum(per) / len(per)
             b = BYTES_PER_MATRIX[(dtype_key, vectors)] * nn
@@ -249,6 +251,7 @@ def main():
         A = gen.spd_fe(n, seed=2, device=dev)
         Af = A.float()
         run_variant("spd_fe_64m_f32r_soa", Af, "soa", True, "f32r")
+        run_variant("spd_fe_64m_f32_unrefined_soa", Af, "soa", True, "f32")
         run_variant("spd_fe_64m_f64_soa_valsonly", A, "soa", False, "f64")
         Aa = A.t().contiguous()
         run_variant("spd_fe_64m_f64_aos", Aa, "aos", True, "f64")
@@ -276,6 +279,8 @@ def main():
         line["variants"] = side
         try:
             line["f32r_error_vs_fp64_oracle"] = f32r_errors(torch, gen, s3)
+            line["f32_unrefined_error_vs_fp64_oracle"] = f32r_errors(torch, gen, s3,
+                                                                     refine=False)
         except Exception as exc:  # report, do not hide the headline
             line["f32r_error_vs_fp64_oracle"] = {"error": repr(exc)}
         if not args.no_serving:

@@ -31,8 +31,8 @@
  * Eigenvalues are in ascending order; column c of V belongs to lambda c.
  * The sign of each eigenvector, and the basis inside an eigenspace of a
  * repeated eigenvalue, are whatever the method produces.
- * dtype SYEV3_F64: every array is double.  dtype SYEV3_F32_REFINE: every
- * array is float; the arithmetic is mixed (see below).
+ * dtype SYEV3_F64: every array is double.  dtypes SYEV3_F32_REFINE and
+ * SYEV3_F32: every array is float; the arithmetic is mixed (see below).
  * V may be NULL: eigenvalues only.
  *
  * Memory: every pointer is device memory owned by the caller, alive until
@@ -65,6 +65,12 @@ extern "C" {
 #define SYEV3_F32_REFINE 1   /* FP32 storage; FP64 reduction, deflation test
                                 and eigenvectors, FP32 zero finder followed
                                 by one FP64 Newton step per root */
+#define SYEV3_F32 2          /* as SYEV3_F32_REFINE without the refinement:
+                                the FP32 zeros are used unrefined and the
+                                vectors come from the formulas of Sec. 1
+                                without re-orthogonalisation.  For measuring
+                                what the refinement buys (an ablation); the
+                                server does not accept it */
 
 /* layouts */
 #define SYEV3_SOA 0

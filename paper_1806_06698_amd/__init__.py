@@ -16,11 +16,11 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (AOS, AOS9, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD,
+from ._lib import (AOS, AOS9, F32, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD,
                    FLAG_SIMPLIFIED_DEFLATION, SOA, Syev3Error)
 
 __all__ = ["syev3", "syev3_inplace", "batched_syev3", "batched_syev3_ex", "batched_syev3_info",
-           "F64", "F32_REFINE", "SOA", "AOS", "AOS9", "FLAG_SIMPLIFIED_DEFLATION",
+           "F64", "F32_REFINE", "F32", "SOA", "AOS", "AOS9", "FLAG_SIMPLIFIED_DEFLATION",
            "FLAG_NO_H_GUARD", "FLAG_NEWTON", "Syev3Error", "lib_path"]
 
 lib_path = _lib.LIB_PATH
@@ -53,16 +53,17 @@ def batched_syev3_info(n, A_ptr, ld, layout, lam_ptr, V_ptr, dtype, flags,
                                          dtype, flags, info_ptr, stream_handle)
 
 
-def _dtype_code(t: torch.Tensor) -> int:
+def _dtype_code(t: torch.Tensor, refine: bool = True) -> int:
     if t.dtype == torch.float64:
         return F64
     if t.dtype == torch.float32:
-        return F32_REFINE
+        return F32_REFINE if refine else F32
     raise TypeError(f"A must be float64 or float32, got {t.dtype}")
 
 
 def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
-          flags: int = 0, info: bool = False, out=None, stream=None):
+          flags: int = 0, info: bool = False, out=None, stream=None,
+          refine: bool = True):
     """Eigen-decompose a batch of symmetric 3x3 matrices on the GPU.
 
     layout "soa": A has shape (6, n), rows a11 a12 a13 a22 a23 a33, row
@@ -73,14 +74,15 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
     layout "aos9": A holds full matrices, (n, 3, 3) or (n, 9), contiguous
     (only the upper triangle is read); outputs as for "aos".
     float64 input runs the FP64 path; float32 input the FP32-storage path
-    with FP64 refinement.  vectors=False skips V.  info=True also returns the
+    with FP64 refinement (refine=False: the unrefined FP32 ablation,
+    dtype F32).  vectors=False skips V.  info=True also returns the
     per-matrix branch and iteration counts (int32).
     out: optional (lam, V) tensors to write into (same shapes as returned,
     with the input's ld for SoA).
     """
     if not A.is_cuda:
         raise ValueError("A must be a GPU tensor (the solver has no CPU path)")
-    dt = _dtype_code(A)
+    dt = _dtype_code(A, refine)
     if layout == "soa":
         if A.dim() != 2 or A.shape[0] != 6 or A.stride(1) != 1:
             raise ValueError("SoA input must have shape (6, n) with unit column stride")

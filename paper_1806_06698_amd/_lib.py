@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(_PKG, "libsyev3.so")
 
 F64 = 0
 F32_REFINE = 1
+F32 = 2
 SOA = 0
 AOS = 1
 AOS9 = 2

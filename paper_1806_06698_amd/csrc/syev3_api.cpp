@@ -30,7 +30,8 @@ Range span(const void* p, int64_t n, int64_t ld, int layout, int planes,
 
 int check_args(int64_t n, const void* A, int64_t& ld, int layout,
                const void* lambda, const void* V, int dtype, uint32_t flags) {
-  if (dtype != SYEV3_F64 && dtype != SYEV3_F32_REFINE) return SYEV3_E_DTYPE;
+  if (dtype != SYEV3_F64 && dtype != SYEV3_F32_REFINE && dtype != SYEV3_F32)
+    return SYEV3_E_DTYPE;
   if (flags & ~SYEV3_FLAGS_ALL) return SYEV3_E_FLAGS;
   if ((flags & SYEV3_FLAG_NEWTON) && dtype != SYEV3_F64) return SYEV3_E_DTYPE;
   if (layout != SYEV3_SOA && layout != SYEV3_AOS && layout != SYEV3_AOS9)

@@ -168,6 +168,7 @@ hipError_t launch_batched(int64_t n, const void* A, int64_t ld, int layout,
                           int32_t* info, hipStream_t stream) {
   if (dtype == 0)
     return launch_dt<double>(n, A, ld, layout, lambda, V, flags, info, stream);
+  if (dtype == 2) flags |= kFlagUnrefined;
   return launch_dt<float>(n, A, ld, layout, lambda, V, flags, info, stream);
 }
 

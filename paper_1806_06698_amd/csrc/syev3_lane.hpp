@@ -47,6 +47,9 @@ constexpr int kMaxIter32 = 24;   // FP32 zero-finder evaluations per root
 constexpr uint32_t kFlagSimplified = 1u;
 constexpr uint32_t kFlagNoHGuard = 2u;
 constexpr uint32_t kFlagNewton = 4u;
+// internal: FP32 zero finder without the FP64 Newton step and without the
+// re-orthogonalisation (an ablation of the refinement); never set by callers
+constexpr uint32_t kFlagUnrefined = 1u << 31;
 
 enum Branch : int { kZero = 0, kNonFinite = 1, kDiagonal = 2, kDeflated = 3,
                     kReduced = 4 };
@@ -401,7 +404,9 @@ __device__ __forceinline__ double newton_refine(const Arrow1& P, double x, bool&
 // ---------------------------------------------------------------------------
 // The whole solve.  Input: the 6 unique entries (any doubles).  Output: lam
 // ascending, V[3r + c] = row r of eigenvector c.  F32R selects the FP32 zero
-// finder with FP64 refinement and an FP64 re-orthogonalisation.
+// finder with FP64 refinement and an FP64 re-orthogonalisation; with
+// kFlagUnrefined the FP32 zeros are used as they are, with the paper's
+// vector formulas (zeros the FP32 finder cannot give still go to FP64 BG).
 // Returns branch | it_mu << 8 | it_nu << 16.
 // ---------------------------------------------------------------------------
 struct Vec3 {
@@ -532,8 +537,13 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
       fb = fb || !c1 || !c2 || !(y1 > 0x1p-100f) || !(y2 > 0x1p-100f);
       bool bad1 = false, bad2 = false;
       if (!fb) {
-        mu = newton_refine(P1, (double)y1, bad1);
-        nu = newton_refine(P2, (double)y2, bad2);
+        if (flags & kFlagUnrefined) {
+          mu = (double)y1;
+          nu = (double)y2;
+        } else {
+          mu = newton_refine(P1, (double)y1, bad1);
+          nu = newton_refine(P2, (double)y2, bad2);
+        }
       }
       if (fb || bad1 || bad2) {
         // near-degenerate root isolation falls back to the FP64 zero finder
@@ -557,7 +567,7 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
       const Vec3 u3{be1 * nu, be2 * nua, -nu * nua};
       v2 = normalized(u1);
       v0 = normalized(u3);
-      if (F32R) {
+      if (F32R && !(flags & kFlagUnrefined)) {
         // one Gram-Schmidt re-orthogonalisation: u3 against u1, then the
         // middle vector as their cross product (the paper's u2 is u1 x u3
         // up to a positive factor), orthogonal to both by construction

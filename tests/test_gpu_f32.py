@@ -1,0 +1,119 @@
+"""FP32-storage forms (dtypes F32_REFINE and F32) against the FP64 oracle on
+the same inputs: the FP32 values, widened exactly.
+
+Bars, in units of eps32 = 2^-23 (u = eps32 / 2 is the FP32 rounding unit):
+
+F32_REFINE.  The arrow, the deflation test and the vectors are FP64; the
+FP32 zeros get one FP64 Newton step (Sec. 1.4.2), which leaves an error of
+at most 2^-12 of the FP32 zero's own error (a larger correction sends the
+lane to the FP64 zero finder).  What remains is the rounding of the outputs
+to FP32: |dlambda_i| <= u |lambda_i| <= u ||A||_F, ||dV||_F <= u sqrt(3).
+  |lambda_i - lambda_ref_i| <= 1 eps32 ||A||_F         (bound 0.5, plus FP64 noise)
+  ||A V - V Lambda||_F      <= 3 eps32 ||A||_F         (2 ||A|| ||dV|| + ||dLambda||: 2.23)
+  ||V^T V - I||_F           <= 3 eps32                 (2 ||dV||: 1.73)
+
+F32 (the ablation: no Newton step, no re-orthogonalisation).  A zero of the
+FP32-rounded arrow is off by |df| / f' with f' >= 1; rounding the four
+coefficients perturbs f at the zero by at most u (3 |gamma_bar| + 2 mu), the
+FP32 evaluation of f adds a few u (|gamma_bar| + mu), and the stop test
+leaves at most 4 eps32 mu; with |gamma_bar|, mu <= 2 ||A||_F and lambda_2
+carrying both zeros' errors, the first-order sum stays under 32 eps32 ||A||_F.
+  |lambda_i - lambda_ref_i| <= 32 eps32 ||A||_F
+Its vectors are only reported: the orthogonality of u1 and u3 needs mu and
+nu to be accurate relative to themselves (Sec. 1.3), and an FP32 zero of a
+problem whose gamma_bar is much larger than the zero is not.
+"""
+import numpy as np
+import pytest
+import torch
+
+import checks
+import oracle
+import paper_1806_06698_amd as s3
+from gpu_common import EPS32, EPS64, need_gpu, soa_to_numpy, solve_soa
+from paper_1806_06698_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+BAR_REFINE = {"lam": 1.0, "res": 3.0, "orth": 3.0}
+BAR_UNREFINED_LAM = 32.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    oracle.build(force=False)
+
+
+def _inputs(kind, n, seed):
+    """FP32 inputs (6, n) on the CPU."""
+    if kind == "pow2_range":
+        # N(0,1) matrices scaled by 2^k, k uniform in [-100, 100]: the power-
+        # of-two scaling over most of the FP32 exponent range
+        rng = np.random.default_rng(seed)
+        A = gen.normal(n, seed)
+        k = torch.from_numpy(rng.integers(-100, 101, size=n).astype(np.float64))
+        return (A * torch.pow(2.0, k)).float()
+    A, _ = gen.make(kind, n, seed)
+    return A.float()
+
+
+def _measure(A32, refine):
+    A6 = gen.to_aos(A32.double()).numpy()
+    lam_d, V_d = solve_soa(A32.cuda(), refine=refine)
+    assert lam_d.dtype == torch.float32 and V_d.dtype == torch.float32
+    lam, V = soa_to_numpy(lam_d, V_d)
+    lam_o, _ = oracle.solve(A6)
+    to32 = EPS64 / EPS32
+    eerr = checks.eig_error(A6, lam, lam_o) * to32
+    res = checks.residual(A6, lam, V) * to32
+    orth = checks.orthogonality(V) * to32
+    return lam, eerr, res, orth
+
+
+@pytest.mark.parametrize("kind,n,seed", [
+    ("normal", 3 * 65536 + 17, 20),   # several tiles and a ragged tail
+    ("stress_mix", 200_003, 21),
+    ("spd_fe", 100_001, 22),
+    ("uniform", 50_000, 23),
+    ("chi2", 50_000, 24),
+    ("pow2_range", 100_003, 25),
+])
+def test_refined_fp32_form_against_the_oracle(kind, n, seed):
+    A32 = _inputs(kind, n, seed)
+    lam, eerr, res, orth = _measure(A32, refine=True)
+    print(f"F32_REFINE {kind} n={n} max |dlam|/(eps32|A|) {eerr.max():.3f} "
+          f"res {res.max():.3f} orth {orth.max():.3f} (eps32)", flush=True)
+    assert np.all(np.diff(lam, axis=1) >= 0)
+    assert eerr.max() <= BAR_REFINE["lam"]
+    assert res.max() <= BAR_REFINE["res"]
+    assert orth.max() <= BAR_REFINE["orth"]
+
+
+@pytest.mark.parametrize("kind,n,seed", [
+    ("normal", 3 * 65536 + 17, 30),
+    ("stress_mix", 200_003, 31),
+    ("spd_fe", 100_001, 32),
+])
+def test_unrefined_fp32_ablation(kind, n, seed):
+    A32 = _inputs(kind, n, seed)
+    lam, eerr, res, orth = _measure(A32, refine=False)
+    q = lambda x: f"{np.median(x):.3g}/{np.percentile(x, 99):.3g}/{x.max():.3g}"
+    print(f"F32 (unrefined) {kind} n={n} |dlam|/(eps32|A|) {q(eerr)} "
+          f"res {q(res)} orth {q(orth)} (median/p99/max, eps32)", flush=True)
+    assert np.all(np.diff(lam, axis=1) >= 0)
+    assert eerr.max() <= BAR_UNREFINED_LAM
+    assert np.all(np.isfinite(res)) and np.all(np.isfinite(orth))
+
+
+def test_refinement_is_the_only_difference_on_exact_cases():
+    """Diagonal and deflated matrices never reach the zero finder, so the
+    two FP32 forms give the same bits there."""
+    A, cat = gen.stress_mix(65_536, seed=33)
+    A32 = A.float()
+    keep = (cat == gen.CAT_DIAGONAL)
+    Ad = A32[:, keep].contiguous().cuda()
+    l1, V1 = solve_soa(Ad, refine=True)
+    l2, V2 = solve_soa(Ad, refine=False)
+    assert Ad.shape[1] > 1000
+    assert torch.equal(l1, l2) and torch.equal(V1, V2)

@@ -266,3 +266,30 @@ def test_full_matrix_layout_and_in_place():
     lam_fa, V_fa = s3.syev3(gen.to_aos(A).float().cuda(), layout="aos")
     torch.cuda.synchronize()
     assert torch.equal(lam_f, lam_fa) and torch.equal(f32, V_fa)
+
+
+@pytest.mark.parametrize("layout", [s3.SOA, s3.AOS])
+def test_adjacent_arrays_in_one_buffer_are_accepted(layout):
+    """A, lambda and V back to back in one allocation touch but do not
+    overlap: the call is accepted and gives the same bits as separate
+    buffers."""
+    n = 1000
+    A, _ = gen.make("normal", n, 40)
+    if layout == s3.SOA:
+        lam_ref, V_ref = s3.syev3(A.cuda())
+    else:
+        lam_ref, V_ref = s3.syev3(gen.to_aos(A).cuda(), layout="aos")
+    buf = torch.empty(18 * n, dtype=torch.float64, device="cuda")
+    src = A if layout == s3.SOA else gen.to_aos(A)
+    buf[:6 * n].copy_(src.reshape(-1).cuda())
+    p = buf.data_ptr()
+    rc = s3.batched_syev3_ex(n, p, 0, layout, p + 8 * 6 * n, p + 8 * 9 * n, s3.F64, 0,
+                             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert rc == 0
+    if layout == s3.SOA:
+        assert torch.equal(buf[6 * n:9 * n].view(3, n), lam_ref)
+        assert torch.equal(buf[9 * n:].view(9, n), V_ref)
+    else:
+        assert torch.equal(buf[6 * n:9 * n].view(n, 3), lam_ref)
+        assert torch.equal(buf[9 * n:].view(n, 3, 3), V_ref)
