@@ -265,6 +265,50 @@ __device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop)
   return xn;
 }
 
+// One Borges-Gragg step from x on either side of the zero, for continuing
+// from an approximate zero (Sec. 1.4.1: the iteration converges
+// monotonically from any start in (0, inf)).  Right of the zero it is
+// bg_step's step.  Left of it (f(x) < 0) the model zero moves right and stays
+// left of the zero, since f - phi_j = -(w0 - 1)(x - x_j)^3 / (x (x + ab)) is
+// negative there.  With f < 0 and a < 0, b^2 + 4af exceeds b^2, so the
+// increment has no cancellation as 2f / (b + sqrt(b^2 + 4af)) for b >= 0 nor
+// as (sqrt(b^2 + 4af) - b) / (2a) for b < 0 (b = f' + f/x is negative where
+// f/x < -f').  Stop left of the zero: zero - x_new < |f(x_new)| / f'(c) <=
+// |f(x_new)| (f' >= 1, the bound of Sec. 1.4.2), |f(x_new)| from the closed
+// form above; right of it: bg_step's test.
+__device__ __forceinline__ double bg_step_either(const Arrow1& P, double x, bool& stop) {
+  const Spec s = spec_eval(P, x);
+  const bool left = s.f < 0.0;
+  const double w0m1 = (s.q2 * P.ab) * (s.rp * s.rp);
+  const double w0 = w0m1 + 1.0;
+  const double a = -w0 * s.rx;
+  const double b = __builtin_fma(s.f, s.rx, s.fp);
+  const double disc = __builtin_fmax(0x1p-1000, __builtin_fma(b, b, 4.0 * a * s.f));
+  const double sq = sqrt1(disc);
+  const bool conj = b < 0.0;
+  const double dl = (conj ? sq - b : 2.0 * s.f) * rcp1(conj ? 2.0 * a : b + sq);
+  double xn;
+  if (dl <= 0.5 * x) {
+    xn = x - dl;
+  } else {
+    // right of the zero, a step of more than half of x: the model zero
+    // directly, as in bg_step
+    const double r = x * s.rp;
+    const double w1 = __builtin_fma(P.b2s * r, r * r, P.b1s);
+    const double sigma = (w0 * x - w1 * s.rx) - s.f;
+    const double sq2 = sqrt2(__builtin_fma(sigma, sigma, 4.0 * w0 * w1));
+    xn = sigma >= 0.0 ? ddiv(sigma + sq2, 2.0 * w0) : ddiv(2.0 * w1, sq2 - sigma);
+  }
+  if (left ? !(xn > x) : !(xn < x)) {
+    stop = true;
+    return x;
+  }
+  const double D = dabs(x - xn);
+  if (w0m1 * (D * D) * D <= 2.0 * kEps64 * (xn * xn) * (xn + P.ab) * (left ? 1.0 : s.fp))
+    stop = true;
+  return xn;
+}
+
 // Newton from the left (Sec. 1.4.2): x0 where f meets -b2^2/(x + ab),
 // i.e. x0 = gb/2 + sqrt((gb/2)^2 + b1^2); stop when |f| < 2 eps x.
 __device__ __forceinline__ double newton_start(const Arrow1& P) {
@@ -545,12 +589,25 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
           nu = newton_refine(P2, (double)y2, bad2);
         }
       }
-      if (fb || bad1 || bad2) {
-        // near-degenerate root isolation falls back to the FP64 zero finder
+      if (fb) {
+        // no usable FP32 zero: the FP64 zero finder from its own start
         int j1, j2;
         zeros_bg(P1, P2, mu, nu, j1, j2);
         it1 += j1;
         it2 += j2;
+      } else if (bad1 || bad2) {
+        // The FP32 zero was too far off for one Newton step (a zero small
+        // next to |gamma_bar|, which FP32 cannot resolve): continue with FP64
+        // Borges-Gragg steps.  f is concave, so the Newton iterate lies left
+        // of the zero; when it is not positive the FP32 zero was right of it.
+        if (bad1 && !(mu > 0.0)) mu = (double)y1;
+        if (bad2 && !(nu > 0.0)) nu = (double)y2;
+        bool s1 = !bad1, s2 = !bad2;
+        for (int k = 0; k < kMaxIter; ++k) {
+          if (s1 && s2) break;
+          if (!s1) { ++it1; mu = bg_step_either(P1, mu, s1); }
+          if (!s2) { ++it2; nu = bg_step_either(P2, nu, s2); }
+        }
       }
     } else if (flags & kFlagNewton) {
       zeros_newton(P1, P2, mu, nu, it1, it2);
