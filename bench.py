@@ -122,11 +122,23 @@ def cpu_baseline(torch, gen, target_s):
         dt = time.perf_counter() - t0
         if dt >= target_s:
             break
+    # one core: the first 2^18 matrices of the same sample, about 3 s
+    m1 = 1 << 18
+    reps1, t1 = 0, time.perf_counter()
+    while True:
+        oracle.solve(A6[:m1], nthreads=1)
+        reps1 += 1
+        dt1 = time.perf_counter() - t1
+        if dt1 >= min(3.0, target_s):
+            break
     return {"value": reps * m / dt, "unit": "eigensolves/s (vals+vecs)", "cores": threads,
             "kind": "oracle",
             "sample": f"{m} matrices of the SPD workload's generator (CPU draw, seed 2), "
                       f"FP64 vals+vecs, solved {reps} times in {dt:.1f} s on {threads} "
-                      f"threads"}
+                      f"threads",
+            "value_1_core": reps1 * m1 / dt1,
+            "sample_1_core": f"the first {m1} of those matrices, solved {reps1} times in "
+                             f"{dt1:.1f} s on 1 thread"}
 
 
 def f32r_errors(torch, gen, s3, n_sample=200_000, refine=True):
