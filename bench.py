@@ -168,6 +168,28 @@ def f32r_errors(torch, gen, s3, n_sample=200_000, refine=True):
                                  "on lambda_min are not resolvable"}
 
 
+def zero_finder_stats(torch, s3, A):
+    """Branches and zero-finder evaluations on the headline workload, from
+    one untimed launch that also writes the per-matrix info word."""
+    _, _, info = s3.syev3(A, info=True)
+    br = info & 0xFF
+    it = torch.stack([(info >> 8) & 0xFF, (info >> 16) & 0xFF])
+    red = br == 4
+    trips = it.max(0).values
+    w = trips.numel() // 64 * 64
+    wave_max = trips[:w].view(-1, 64).max(1).values.double()
+    counts = torch.bincount(br.long(), minlength=5).tolist()
+    out = {"branch_counts_[zero,nonfinite,diagonal,deflated,reduced]": counts,
+           "evaluations_per_root_mean_[mu,nu]": [float(it[0][red].double().mean()),
+                                                   float(it[1][red].double().mean())],
+           "evaluations_per_root_max": int(it.max()),
+           "wavefront_max_trips_mean": float(wave_max.mean()),
+           "wavefront_max_trips_max": int(wave_max.max())}
+    del info, it, trips, wave_max, br, red
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -240,6 +262,7 @@ def main():
                      "frac_of_stream_ceiling": ms_ref / ms_launch},
         "kernel_hash": khash,
     }
+    line["zero_finder"] = zero_finder_stats(torch, s3, A)
     del A, lam, V
     torch.cuda.empty_cache()
 
