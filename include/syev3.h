@@ -246,7 +246,10 @@ int syev3_server_submit_host(syev3_server* s, int64_t request, const void* host_
  * in seconds. */
 int syev3_server_poll(syev3_server* s, int64_t request, double* latency_s);
 
-/* Block until the request completes or timeout_s passes (< 0: no limit). */
+/* Block until the request completes or timeout_s passes (< 0: no limit).
+ * Returns 1 when complete, SYEV3_E_TIMEOUT, SYEV3_E_HIP if its tick failed,
+ * or SYEV3_E_STATE if the id is stale, which includes a release of the
+ * request by another thread during the wait. */
 int syev3_server_wait(syev3_server* s, int64_t request, double timeout_s,
                       double* latency_s);
 

@@ -116,6 +116,7 @@ struct syev3_server {
 
 namespace {
 
+// id = gen << 32 | slot, with gen kept to 31 bits so that ids stay positive
 int64_t make_id(int slot, uint32_t gen) { return ((int64_t)gen << 32) | (int64_t)slot; }
 
 Request* lookup(syev3_server* s, int64_t id, int* slot_out) {
@@ -468,12 +469,16 @@ int syev3_server_wait(syev3_server* s, int64_t id, double timeout_s, double* lat
   std::unique_lock<std::mutex> lk(s->mu);
   Request* r = lookup(s, id, nullptr);
   if (!r || r->state == kAdmitted) return SYEV3_E_STATE;
-  auto done = [&] { return r->state == kDone; };
+  // another thread may release the request while this one waits (and the
+  // slot may be acquired again): that ends the wait with E_STATE
+  const uint32_t gen = r->gen;
+  auto done = [&] { return r->gen != gen || r->state == kDone; };
   if (timeout_s < 0) {
     s->cv_done.wait(lk, done);
   } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
     return SYEV3_E_TIMEOUT;
   }
+  if (r->gen != gen) return SYEV3_E_STATE;
   if (r->failed) return SYEV3_E_HIP;
   if (latency_s) *latency_s = seconds_since(r->t_submit, r->t_done);
   return 1;
@@ -488,7 +493,8 @@ int syev3_server_release(syev3_server* s, int64_t id) {
   s->alloc->release(r->off, r->bytes);
   s->st.pool_bytes_in_use = s->alloc->in_use();
   r->state = kFree;
-  r->gen++;
+  s->cv_done.notify_all();  // a waiter on this id ends with E_STATE
+  r->gen = (r->gen + 1) & 0x7fffffffu;
   s->free_slots.push_back(slot);
   return SYEV3_OK;
 }
@@ -579,12 +585,16 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
         char* sink = (char*)o->sink;
         rc = syev3_server_submit_host(s, id, src, sink,
                                       o->want_vectors ? sink + 3 * (size_t)a.n * es : nullptr);
-        if (rc != SYEV3_OK) break;
+        if (rc != SYEV3_OK) {
+          (void)syev3_server_release(s, id);  // still admitted: give its memory back
+          break;
+        }
       } else {
         const int64_t off = (int64_t)(U(rng) * (double)(o->src_n - a.n + 1));
         if (hipMemcpy2DAsync(b.A, (size_t)a.n * es, src + (size_t)off * es,
                              (size_t)o->src_n * es, (size_t)a.n * es, 6,
                              hipMemcpyDeviceToDevice, prod) != hipSuccess) {
+          (void)syev3_server_release(s, id);
           rc = SYEV3_E_HIP;
           break;
         }

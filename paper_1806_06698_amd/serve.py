@@ -47,11 +47,56 @@ def _bind(L):
     return L
 
 
+def check_host_buffers(n, dtype, host_A, host_lam, host_V=None):
+    """The host buffers of a host-staged request of n matrices: contiguous
+    CPU tensors of the request's dtype holding at least 6n, 3n and 9n
+    values (the server copies exactly that many in and out)."""
+    tdt = torch.float64 if dtype == _lib.F64 else torch.float32
+    for name, t, k in (("host_A", host_A, 6), ("host_lam", host_lam, 3), ("host_V", host_V, 9)):
+        if t is None:
+            if name == "host_V":
+                continue
+            raise ValueError(f"{name} is required")
+        if t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CPU tensor")
+        if t.dtype != tdt:
+            raise ValueError(f"{name} must be {tdt} for this request, got {t.dtype}")
+        if t.numel() < k * n:
+            raise ValueError(f"{name} holds {t.numel()} values; the request needs {k * n}")
+
+
+def check_loadgen_sources(src_f64, src_f32, max_log2_n, sink):
+    """Sources of the load generator: (6, src_n) float64 and float32 tensors
+    with the same src_n, contiguous, both on the GPU (inputs copied on the
+    device) or both in host memory with a host sink of at least
+    12 * 2^max_log2_n doubles (host-staged).  The native generator reads
+    them through raw pointers, so a short or mistyped source would be read
+    out of bounds."""
+    for name, t, dt in (("src_f64", src_f64, torch.float64), ("src_f32", src_f32, torch.float32)):
+        if t.dim() != 2 or t.shape[0] != 6 or not t.is_contiguous() or t.dtype != dt:
+            raise ValueError(f"{name} must be a contiguous (6, src_n) {dt} tensor")
+    if src_f64.shape[1] != src_f32.shape[1] or src_f64.shape[1] < 1:
+        raise ValueError("src_f64 and src_f32 must have the same src_n >= 1")
+    if src_f64.is_cuda != src_f32.is_cuda:
+        raise ValueError("both sources on the GPU, or both in host memory")
+    if not src_f64.is_cuda:
+        if sink is None or sink.is_cuda or not sink.is_contiguous():
+            raise ValueError("host-staged load needs a contiguous pinned host sink")
+        if 2.0 ** max_log2_n > src_f64.shape[1]:
+            raise ValueError("host-staged requests take their input from the first 6n "
+                             "source values: src_n must be >= 2^max_log2_n")
+        need = 12 * int(2.0 ** max_log2_n) * 8
+        if sink.numel() * sink.element_size() < need:
+            raise ValueError(f"sink holds {sink.numel() * sink.element_size()} bytes; "
+                             f"requests up to 2^max_log2_n matrices need {need}")
+
+
 class Request:
     """An admitted request: device tensors over the server's pool."""
 
     def __init__(self, server, rid, bufs: RequestBuffers, dtype):
         self.server, self.id, self.n = server, rid, bufs.n
+        self.dtype = bufs.dtype
         tdt = torch.float64 if bufs.dtype == _lib.F64 else torch.float32
         es = 8 if tdt == torch.float64 else 4
         self.A = _tensor_at(bufs.A, (6, bufs.n), tdt, es)
@@ -118,9 +163,7 @@ class Server:
         """Host-staged submission: host_A (6, n), host_lam (3, n), host_V
         (9, n) are CPU tensors of the request's dtype, preferably pinned; the
         server copies A in before the tick and the results out after it."""
-        for t in (host_A, host_lam) + ((host_V,) if host_V is not None else ()):
-            if t.is_cuda or not t.is_contiguous():
-                raise ValueError("host buffers must be contiguous CPU tensors")
+        check_host_buffers(req.n, req.dtype, host_A, host_lam, host_V)
         _lib.check(self.L.syev3_server_submit_host(
             self.h, req.id, host_A.data_ptr(), host_lam.data_ptr(),
             host_V.data_ptr() if host_V is not None else None), "syev3_server_submit_host")
@@ -151,9 +194,8 @@ class Server:
         `concurrency` requests in flight.  Sources on the device: inputs are
         copied on the device.  Sources in (pinned) host memory together with a
         host `sink`: host-staged requests."""
+        check_loadgen_sources(src_f64, src_f32, max_log2_n, sink)
         staged = not src_f64.is_cuda
-        if staged and sink is None:
-            raise ValueError("host-staged load needs a pinned host sink")
         o = LoadgenOpts(qps=qps, closed_concurrency=concurrency,
                         duration_s=duration_s, max_log2_n=max_log2_n,
                         frac_f32=frac_f32, seed=seed, src_f64=src_f64.data_ptr(),
