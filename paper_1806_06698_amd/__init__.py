@@ -61,6 +61,19 @@ def _dtype_code(t: torch.Tensor, refine: bool = True) -> int:
     raise TypeError(f"A must be float64 or float32, got {t.dtype}")
 
 
+def _check_out(t, shape, strides, A, name):
+    """An output tensor the kernels will write through its data pointer:
+    exactly the shape, strides, dtype and device they assume (the
+    library checks only pointers and aliasing)."""
+    if t is None:
+        raise ValueError(f"out: {name} is required")
+    if (tuple(t.shape) != shape or t.dtype != A.dtype or t.device != A.device
+            or (t.numel() > 1 and tuple(t.stride()) != strides)):
+        raise ValueError(f"out: {name} must be a {A.dtype} tensor of shape {shape} with "
+                         f"strides {strides} on {A.device}, got {tuple(t.shape)}, "
+                         f"{tuple(t.stride())}, {t.dtype}, {t.device}")
+
+
 def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
           flags: int = 0, info: bool = False, out=None, stream=None,
           refine: bool = True):
@@ -95,8 +108,11 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
             lam, V = lam_buf[:, :n], (V_buf[:, :n] if vectors else None)
         else:
             lam, V = out
-            if lam.stride(0) != ld or (V is not None and V.stride(0) != ld):
-                raise ValueError("output plane stride must equal the input's")
+            _check_out(lam, (3, n), (ld, 1), A, "lam")
+            if vectors:
+                _check_out(V, (9, n), (ld, 1), A, "V")
+            else:
+                V = None
         lay = SOA
     elif layout in ("aos", "aos9"):
         width = 6 if layout == "aos" else 9
@@ -112,6 +128,11 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
             V = torch.empty((n, 3, 3), dtype=A.dtype, device=A.device) if vectors else None
         else:
             lam, V = out
+            _check_out(lam, (n, 3), (3, 1), A, "lam")
+            if vectors:
+                _check_out(V, (n, 3, 3), (9, 3, 1), A, "V")
+            else:
+                V = None
         lay = AOS if layout == "aos" else AOS9
     else:
         raise ValueError(f"unknown layout {layout!r}")

@@ -1,0 +1,30 @@
+"""Output-tensor checks of the Python binding (no GPU): the kernels write
+through raw pointers, so an out= tensor must have exactly the shape, strides,
+dtype and device they assume."""
+import pytest
+import torch
+
+import paper_1806_06698_amd as s3
+
+
+def test_out_tensors_are_checked():
+    n = 10
+    A = torch.zeros(6, n, dtype=torch.float64)
+    ok_lam = torch.empty(3, n, dtype=torch.float64)
+    s3._check_out(ok_lam, (3, n), (n, 1), A, "lam")
+    wide = torch.empty(3, 2 * n, dtype=torch.float64)[:, :n]       # ld = 2n
+    s3._check_out(wide, (3, n), (2 * n, 1), A, "lam")
+    with pytest.raises(ValueError):
+        s3._check_out(wide, (3, n), (n, 1), A, "lam")                # stride differs from A's
+    with pytest.raises(ValueError):
+        s3._check_out(torch.empty(3, n - 1, dtype=torch.float64), (3, n), (n, 1), A, "lam")
+    with pytest.raises(ValueError):
+        s3._check_out(torch.empty(3, n, dtype=torch.float32), (3, n), (n, 1), A, "lam")
+    with pytest.raises(ValueError):
+        s3._check_out(torch.empty(n, 3, dtype=torch.float64).t(), (3, n), (n, 1), A, "lam")
+    with pytest.raises(ValueError):
+        s3._check_out(None, (9, n), (n, 1), A, "V")
+    aos = torch.empty(n, 3, 3, dtype=torch.float64)
+    s3._check_out(aos, (n, 3, 3), (9, 3, 1), A, "V")
+    with pytest.raises(ValueError):
+        s3._check_out(aos.transpose(1, 2), (n, 3, 3), (9, 3, 1), A, "V")
