@@ -187,8 +187,7 @@ __device__ __forceinline__ Spec spec_eval(const Arrow1& P, double x) {
 // In a CPU emulation of this arithmetic, two chords leave under 1% of zeros
 // needing a third evaluation of f (x_inf alone: 10%); on the GPU two chords
 // time best (one chord costs about what it saves in zero-finder trips from
-// the third on).  An iterate that rounding puts left of the zero is caught by
-// the step (f <= 0).  rab = 1/ab.
+// the third on).  rab = 1/ab.
 // quad_zero(c, k, a): positive zero of a x^2 - c x - k (a, k > 0), in the
 // form without cancellation.
 __device__ __forceinline__ double quad_zero(double c, double k, double a) {
@@ -213,70 +212,71 @@ __device__ __forceinline__ double bg_start(const Arrow1& P, double rab) {
   return U;
 }
 
-// One Borges-Gragg step from x (to the right of the zero).  Sets stop when
-// the returned value is final:
-//   * f(x) <= 0: x is at or just left of the zero (rounding); returns x
-//     after one Newton step, which from the left converges monotonically
-//     (Sec. 1.4.2);
-//   * the step does not decrease x; returns x;
-//   * the new iterate is the zero to relative precision 2 eps; returns it.
-//     The test is the paper's mean-value bound (x - zero < f(x)/f'(x) for x
-//     right of the zero) applied at x_new, with f(x_new) known in closed
-//     form: f - phi = -b2^2 ab (x - x_j)^3 / ((x_j + ab)^3 x (x + ab)), and
-//     phi(x_new) = 0, so f(x_new) = (w0 - 1) D^3 / (x_new (x_new + ab)),
-//     D = x - x_new; and f'(x_new) > f'(x) since f' decreases.  Hence
-//     x_new - zero < (w0 - 1) D^3 / (x_new (x_new + ab) f'(x)), a bound
-//     cubic in the step, checked without evaluating f at x_new.
-__device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop) {
-  const Spec s = spec_eval(P, x);
-  if (s.f <= 0.0) {
-    stop = true;
-    return x - ddiv(s.f, s.fp);
-  }
-  // model phi = w0 x - sigma - w1/x matching f, f', f'' at x:
-  // w0 = 1 + b2^2 ab / p^3; the increment D solves a D^2 + b D - f = 0 with
-  // a = -w0/x and b = f' + f/x; D = 2f / (b + sqrt(b^2 + 4 a f)).
-  const double w0m1 = (s.q2 * P.ab) * (s.rp * s.rp);
-  const double w0 = w0m1 + 1.0;
-  const double a = -w0 * s.rx;
-  const double b = __builtin_fma(s.f, s.rx, s.fp);
-  const double disc = __builtin_fmax(0x1p-1000, __builtin_fma(b, b, 4.0 * a * s.f));
-  // D to ~2^-46: an overshoot of the zero by the error of D, which cubic
-  // convergence can leave within reach, must stay below the rounding level
-  const double dl = (2.0 * s.f) * rcp1(b + sqrt1(disc));
-  double xn;
-  if (dl <= 0.5 * x) {
-    xn = x - dl;
-  } else {
-    // The step removes more than half of x: take x_new as the zero of
-    // w0 x^2 - sigma x - w1 = 0 directly (no cancellation next to the pole).
-    const double r = x * s.rp;
-    const double w1 = __builtin_fma(P.b2s * r, r * r, P.b1s);
-    const double sigma = (w0 * x - w1 * s.rx) - s.f;
-    const double sq = sqrt2(__builtin_fma(sigma, sigma, 4.0 * w0 * w1));
-    xn = sigma >= 0.0 ? ddiv(sigma + sq, 2.0 * w0) : ddiv(2.0 * w1, sq - sigma);
-  }
-  if (!(xn < x)) {
-    stop = true;
-    return x;
-  }
-  const double D = x - xn;
-  if (w0m1 * (D * D) * D <= 2.0 * kEps64 * (xn * xn) * (xn + P.ab) * s.fp) stop = true;
-  return xn;
+// The same bounds in FP32, from the arrow rounded to FP32 (v_rcp_f32 and
+// v_sqrt_f32 are accurate to about one ulp).  The start only has to be
+// close: the iteration converges from either side (bg_step), and a start
+// within about 1e-5 of the zero still needs a single evaluation of f in
+// FP64.  FP32 is cheaper than the FP64 sequences here, and the FP64 path is
+// limited as much by the clock the chip sustains under FP64 load as by HBM.
+struct Arrow1f {
+  float b1s, b2s, ab, gb;
+};
+
+__device__ __forceinline__ float quad_zero32(float c, float k, float a) {
+  const float c2 = 0.5f * c;
+  const float s = __builtin_fabsf(c2) + __builtin_amdgcn_sqrtf(__builtin_fmaf(c2, c2, a * k));
+  const bool pos = c >= 0.0f;
+  return (pos ? s : k) * __builtin_amdgcn_rcpf(pos ? a : s);
 }
 
-// One Borges-Gragg step from x on either side of the zero, for continuing
-// from an approximate zero (Sec. 1.4.1: the iteration converges
-// monotonically from any start in (0, inf)).  Right of the zero it is
-// bg_step's step.  Left of it (f(x) < 0) the model zero moves right and stays
-// left of the zero, since f - phi_j = -(w0 - 1)(x - x_j)^3 / (x (x + ab)) is
-// negative there.  With f < 0 and a < 0, b^2 + 4af exceeds b^2, so the
-// increment has no cancellation as 2f / (b + sqrt(b^2 + 4af)) for b >= 0 nor
-// as (sqrt(b^2 + 4af) - b) / (2a) for b < 0 (b = f' + f/x is negative where
-// f/x < -f').  Stop left of the zero: zero - x_new < |f(x_new)| / f'(c) <=
-// |f(x_new)| (f' >= 1, the bound of Sec. 1.4.2), |f(x_new)| from the closed
-// form above; right of it: bg_step's test.
-__device__ __forceinline__ double bg_step_either(const Arrow1& P, double x, bool& stop) {
+__device__ __forceinline__ float bg_start32(const Arrow1f& P) {
+  float U = quad_zero32(P.gb, P.b1s + P.b2s, 1.0f);
+  const float b2r = P.b2s * __builtin_amdgcn_rcpf(P.ab);
+  const float c = P.gb + b2r;
+#pragma unroll
+  for (int j = 0; j < kChords; ++j) {
+    const float k = b2r * __builtin_amdgcn_rcpf(U + P.ab);
+    U = __builtin_fminf(U, quad_zero32(c, P.b1s, 1.0f + k));
+  }
+  return U;
+}
+
+// Start of the FP64 iteration: the FP32 bounds when the arrow is well
+// inside FP32's normal range (the squares b^2 and the zero b1^2/|gb| that a
+// tiny b1 gives stay normal, b2^2/ab stays finite), else the FP64 bounds.
+__device__ __forceinline__ double start_point(const Arrow1& P) {
+  const Arrow1f Q{(float)P.b1s, (float)P.b2s, (float)P.ab, (float)P.gb};
+  const bool ok = Q.b1s >= 0x1p-120f && Q.b2s >= 0x1p-120f && Q.ab >= 0x1p-100f;
+  const float u = bg_start32(Q);
+  if (ok && u >= 0x1p-124f && u < 0x1p100f) return (double)u;
+  return bg_start(P, rcp1(P.ab));
+}
+
+// One Borges-Gragg step from x on either side of the zero (Sec. 1.4.1: the
+// iteration converges monotonically from any start in (0, inf)).  Sets stop
+// when the returned value is final.
+//  * The model phi_j = w0 x - sigma - w1/x matches f, f', f'' at x_j, and
+//    f - phi_j = -b2^2 ab (x - x_j)^3 / ((x_j + ab)^3 x (x + ab)) (exactly).
+//    Since phi_j(x_new) = 0, f(x_new) = -(w0 - 1) D^3 / (x_new (x_new + ab))
+//    with D = x_new - x_j: the iterate stays on the side it started from.
+//  * Right of the zero (f > 0) the paper's increment D = 2f / (b + sqrt(b^2
+//    + 4af)), a = -w0/x, b = f' + f/x > 0.  When it removes more than half
+//    of x, x_new is the model zero itself, w0 x^2 - sigma x - w1 = 0, solved
+//    without the cancellation of x - D next to the pole.
+//  * Left of it (f < 0), a < 0 makes b^2 + 4af exceed b^2, so the increment
+//    has no cancellation as 2f / (b + sqrt(b^2 + 4af)) for b >= 0 nor as
+//    (sqrt(b^2 + 4af) - b) / (2a) for b < 0 (b is negative where
+//    f/x < -f').
+//  * Stop right of the zero: the paper's bound x - zero < f(x)/f'(x) at
+//    x_new, with f(x_new) from the closed form and f'(x_new) > f'(x_j) (f'
+//    decreases): x_new - zero < (w0 - 1)|D|^3 / (x_new (x_new + ab) f'(x_j)),
+//    cubic in the step and checked without evaluating f at x_new.  Left of
+//    it: zero - x_new < |f(x_new)| / f'(c) <= |f(x_new)| (f' >= 1, the bound
+//    of Sec. 1.4.2).  Either is compared with 2 eps x_new.  A step that does
+//    not move x towards the zero (rounding at the zero) stops with x.
+// D is computed to about 2^-46: near the zero a cubic step's own error must
+// stay below the rounding level.
+__device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop) {
   const Spec s = spec_eval(P, x);
   const bool left = s.f < 0.0;
   const double w0m1 = (s.q2 * P.ab) * (s.rp * s.rp);
@@ -292,7 +292,6 @@ __device__ __forceinline__ double bg_step_either(const Arrow1& P, double x, bool
     xn = x - dl;
   } else {
     // right of the zero, a step of more than half of x: the model zero
-    // directly, as in bg_step
     const double r = x * s.rp;
     const double w1 = __builtin_fma(P.b2s * r, r * r, P.b1s);
     const double sigma = (w0 * x - w1 * s.rx) - s.f;
@@ -335,9 +334,8 @@ __device__ __forceinline__ double newton_step(const Arrow1& P, double x, bool& s
 // so their latencies overlap; the loop runs until both have stopped.
 __device__ __forceinline__ void zeros_bg(const Arrow1& P1, const Arrow1& P2,
                                          double& x1, double& x2, int& it1, int& it2) {
-  const double rab = rcp1(P1.ab);  // both problems share abar
-  x1 = bg_start(P1, rab);
-  x2 = bg_start(P2, rab);
+  x1 = start_point(P1);
+  x2 = start_point(P2);
   bool s1 = false, s2 = false;
   it1 = 0;
   it2 = 0;
@@ -367,30 +365,6 @@ __device__ __forceinline__ void zeros_newton(const Arrow1& P1, const Arrow1& P2,
 // precision (v_rcp_f32 and v_sqrt_f32 are accurate to about one ulp).
 // conv reports a stop by the precision test or at the zero.
 // ---------------------------------------------------------------------------
-struct Arrow1f {
-  float b1s, b2s, ab, gb;
-};
-
-__device__ __forceinline__ float quad_zero32(float c, float k, float a) {
-  const float c2 = 0.5f * c;
-  const float s = __builtin_fabsf(c2) + __builtin_amdgcn_sqrtf(__builtin_fmaf(c2, c2, a * k));
-  const bool pos = c >= 0.0f;
-  return (pos ? s : k) * __builtin_amdgcn_rcpf(pos ? a : s);
-}
-
-// the same bounds as bg_start
-__device__ __forceinline__ float bg_start32(const Arrow1f& P) {
-  float U = quad_zero32(P.gb, P.b1s + P.b2s, 1.0f);
-  const float b2r = P.b2s * __builtin_amdgcn_rcpf(P.ab);
-  const float c = P.gb + b2r;
-#pragma unroll
-  for (int j = 0; j < kChords; ++j) {
-    const float k = b2r * __builtin_amdgcn_rcpf(U + P.ab);
-    U = __builtin_fminf(U, quad_zero32(c, P.b1s, 1.0f + k));
-  }
-  return U;
-}
-
 __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop, bool& conv) {
   const float p = x + P.ab;
   const float rx = __builtin_amdgcn_rcpf(x);
@@ -605,8 +579,8 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
         bool s1 = !bad1, s2 = !bad2;
         for (int k = 0; k < kMaxIter; ++k) {
           if (s1 && s2) break;
-          if (!s1) { ++it1; mu = bg_step_either(P1, mu, s1); }
-          if (!s2) { ++it2; nu = bg_step_either(P2, nu, s2); }
+          if (!s1) { ++it1; mu = bg_step(P1, mu, s1); }
+          if (!s2) { ++it2; nu = bg_step(P2, nu, s2); }
         }
       }
     } else if (flags & kFlagNewton) {
