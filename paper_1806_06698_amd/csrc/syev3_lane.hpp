@@ -244,12 +244,23 @@ __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
 // Start of the FP64 iteration: the FP32 bounds when the arrow is well
 // inside FP32's normal range (the squares b^2 and the zero b1^2/|gb| that a
 // tiny b1 gives stay normal, b2^2/ab stays finite), else the FP64 bounds.
-__device__ __forceinline__ double start_point(const Arrow1& P) {
+// The chords' constant c = gb + b2^2/ab is formed in FP64: for a zero small
+// next to |gb| its two terms nearly cancel, and FP32 would lose c.
+// rab = 1/ab.
+__device__ __forceinline__ double start_point(const Arrow1& P, double rab) {
   const Arrow1f Q{(float)P.b1s, (float)P.b2s, (float)P.ab, (float)P.gb};
   const bool ok = Q.b1s >= 0x1p-120f && Q.b2s >= 0x1p-120f && Q.ab >= 0x1p-100f;
-  const float u = bg_start32(Q);
-  if (ok && u >= 0x1p-124f && u < 0x1p100f) return (double)u;
-  return bg_start(P, rcp1(P.ab));
+  const double b2r = P.b2s * rab;
+  const float c = (float)(P.gb + b2r);
+  const float b2rf = (float)b2r;
+  float U = quad_zero32(Q.gb, Q.b1s + Q.b2s, 1.0f);
+#pragma unroll
+  for (int j = 0; j < kChords; ++j) {
+    const float k = b2rf * __builtin_amdgcn_rcpf(U + Q.ab);
+    U = __builtin_fminf(U, quad_zero32(c, Q.b1s, 1.0f + k));
+  }
+  if (ok && U >= 0x1p-124f && U < 0x1p100f) return (double)U;
+  return bg_start(P, rab);
 }
 
 // One Borges-Gragg step from x on either side of the zero (Sec. 1.4.1: the
@@ -334,8 +345,9 @@ __device__ __forceinline__ double newton_step(const Arrow1& P, double x, bool& s
 // so their latencies overlap; the loop runs until both have stopped.
 __device__ __forceinline__ void zeros_bg(const Arrow1& P1, const Arrow1& P2,
                                          double& x1, double& x2, int& it1, int& it2) {
-  x1 = start_point(P1);
-  x2 = start_point(P2);
+  const double rab = rcp1(P1.ab);  // both problems share abar
+  x1 = start_point(P1, rab);
+  x2 = start_point(P2, rab);
   bool s1 = false, s2 = false;
   it1 = 0;
   it2 = 0;
