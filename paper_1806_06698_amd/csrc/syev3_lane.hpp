@@ -212,12 +212,13 @@ __device__ __forceinline__ double bg_start(const Arrow1& P, double rab) {
   return U;
 }
 
-// The same bounds in FP32, from the arrow rounded to FP32 (v_rcp_f32 and
-// v_sqrt_f32 are accurate to about one ulp).  The start only has to be
-// close: the iteration converges from either side (bg_step), and a start
-// within about 1e-5 of the zero still needs a single evaluation of f in
-// FP64.  FP32 is cheaper than the FP64 sequences here, and the FP64 path is
-// limited as much by the clock the chip sustains under FP64 load as by HBM.
+// FP32 versions (v_rcp_f32 and v_sqrt_f32 are accurate to about one ulp),
+// for the FP32 zero finder of the FP32-storage form and for the start of the
+// FP64 iteration.  That start only has to be close: the iteration converges
+// from either side (bg_step), and a start within about 1e-5 of the zero
+// still needs a single evaluation of f in FP64.  FP32 is cheaper than the
+// FP64 sequences, and the FP64 path is limited as much by the clock the
+// chip sustains under FP64 load as by HBM.
 struct Arrow1f {
   float b1s, b2s, ab, gb;
 };
@@ -241,24 +242,48 @@ __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
   return U;
 }
 
-// Start of the FP64 iteration: the FP32 bounds when the arrow is well
-// inside FP32's normal range (the squares b^2 and the zero b1^2/|gb| that a
-// tiny b1 gives stay normal, b2^2/ab stays finite), else the FP64 bounds.
-// The chords' constant c = gb + b2^2/ab is formed in FP64: for a zero small
-// next to |gb| its two terms nearly cancel, and FP32 would lose c.
+// Start of the FP64 iteration, in FP32 from the arrow rounded to FP32: a
+// bracket [L, U] of the zero, narrowed twice, and its upper end.
+//  * L0 = the paper's Newton start (Sec. 1.4.2), the zero of x - gb - b1^2/x
+//    (the term b2^2/(x + ab) dropped), a lower bound; U0 = x_inf, an upper
+//    bound (see bg_start).
+//  * Chord of the convex 1/(x + ab) over [L, U]: it lies above the
+//    function there, so x - gb - b1^2/x - b2^2 chord(x) lies below f on
+//    [L, U] and its zero is a new upper bound U.
+//  * Tangent of 1/(x + ab) at U: it lies below the function everywhere, so
+//    the same construction gives a function above f and a new lower bound L.
+//  * A second chord over the narrowed [L, U] gives the start.
+// Each bound is the positive zero of (1 + w) x^2 - c x - b1^2, w the line's
+// slope times -b2^2.  The constants c = gb + b2^2 * (the line's value at 0)
+// are written as c0 + b2^2 ((value at 0) - 1/ab), with c0 = gb + b2^2/ab
+// formed in FP64: for a zero small next to |gb| the terms of c0 nearly
+// cancel, while the differences, -L U / ((L + ab)(U + ab) ab) for a chord
+// and -t^2 / ((t + ab)^2 ab) for the tangent at t, are accurate in FP32.
+// In a CPU emulation this start leaves no zero needing three evaluations of
+// f on the SPD and normal workloads (the two chords over [0, U] of bg_start:
+// about 1%), and the FP32 arithmetic costs less than the trips it saves.
+// It is used when the arrow is well inside FP32's normal range (the squares
+// b^2 and a zero b1^2/|gb| that a tiny b1 gives stay normal, b2^2/ab stays
+// finite); otherwise the FP64 bounds of bg_start.  The start may fall on
+// either side of the zero by FP32 rounding; the step handles both.
 // rab = 1/ab.
 __device__ __forceinline__ double start_point(const Arrow1& P, double rab) {
   const Arrow1f Q{(float)P.b1s, (float)P.b2s, (float)P.ab, (float)P.gb};
   const bool ok = Q.b1s >= 0x1p-120f && Q.b2s >= 0x1p-120f && Q.ab >= 0x1p-100f;
-  const double b2r = P.b2s * rab;
-  const float c = (float)(P.gb + b2r);
-  const float b2rf = (float)b2r;
+  const float c0 = (float)__builtin_fma(P.b2s, rab, P.gb);
+  const float rabf = __builtin_amdgcn_rcpf(Q.ab);
+  float L = quad_zero32(Q.gb, Q.b1s, 1.0f);
   float U = quad_zero32(Q.gb, Q.b1s + Q.b2s, 1.0f);
-#pragma unroll
-  for (int j = 0; j < kChords; ++j) {
-    const float k = b2rf * __builtin_amdgcn_rcpf(U + Q.ab);
-    U = __builtin_fminf(U, quad_zero32(c, Q.b1s, 1.0f + k));
-  }
+  float rl = __builtin_amdgcn_rcpf(L + Q.ab);
+  float ru = __builtin_amdgcn_rcpf(U + Q.ab);
+  float w = Q.b2s * rl * ru;
+  U = __builtin_fminf(U, quad_zero32(c0 - w * (L * U) * rabf, Q.b1s, 1.0f + w));
+  ru = __builtin_amdgcn_rcpf(U + Q.ab);
+  w = Q.b2s * ru * ru;
+  L = __builtin_fmaxf(L, quad_zero32(c0 - w * (U * U) * rabf, Q.b1s, 1.0f + w));
+  rl = __builtin_amdgcn_rcpf(L + Q.ab);
+  w = Q.b2s * rl * ru;
+  U = __builtin_fminf(U, quad_zero32(c0 - w * (L * U) * rabf, Q.b1s, 1.0f + w));
   if (ok && U >= 0x1p-124f && U < 0x1p100f) return (double)U;
   return bg_start(P, rab);
 }
