@@ -219,8 +219,11 @@ __device__ __forceinline__ double bg_start(const Arrow1& P, double rab) {
 // still needs a single evaluation of f in FP64.  FP32 is cheaper than the
 // FP64 sequences, and the FP64 path is limited as much by the clock the
 // chip sustains under FP64 load as by HBM.
+// c0 = gb + b2^2/ab and rab = 1/ab, formed in FP64 and rounded, for the
+// FP32 zero finder of the FP32-storage form (unused by start_point).
 struct Arrow1f {
   float b1s, b2s, ab, gb;
+  float c0 = 0.0f, rab = 0.0f;
 };
 
 __device__ __forceinline__ float quad_zero32(float c, float k, float a) {
@@ -230,10 +233,12 @@ __device__ __forceinline__ float quad_zero32(float c, float k, float a) {
   return (pos ? s : k) * __builtin_amdgcn_rcpf(pos ? a : s);
 }
 
+// The FP64 path's two-chord bounds (bg_start) in FP32; the chords' constant
+// is c0, which FP32 could not form where its terms cancel.
 __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
   float U = quad_zero32(P.gb, P.b1s + P.b2s, 1.0f);
-  const float b2r = P.b2s * __builtin_amdgcn_rcpf(P.ab);
-  const float c = P.gb + b2r;
+  const float b2r = P.b2s * P.rab;
+  const float c = P.c0;
 #pragma unroll
   for (int j = 0; j < kChords; ++j) {
     const float k = b2r * __builtin_amdgcn_rcpf(U + P.ab);
@@ -408,7 +413,11 @@ __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop
   const float rp = __builtin_amdgcn_rcpf(p);
   const float q1 = P.b1s * rx;
   const float q2 = P.b2s * rp;
-  const float f = ((x - P.gb) - q1) - q2;
+  // For x < ab, f = x - c0 - b1^2/x + b2^2 x / (ab (x + ab)) exactly: with
+  // c0 formed in FP64 this keeps a zero that is small next to |gb| (where
+  // gb and b2^2/ab nearly cancel) resolvable in FP32.  For x >= ab the
+  // usual form has no such cancellation.
+  const float f = x < P.ab ? ((x - P.c0) - q1) + q2 * (x * P.rab) : ((x - P.gb) - q1) - q2;
   const float fp = __builtin_fmaf(q1, rx, __builtin_fmaf(q2, rp, 1.0f));
   if (f <= 0.0f) {
     stop = true;
@@ -578,8 +587,11 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
     const Arrow1 P2{b2s, b1s, al, al2 - ga};
     double mu = 0.0, nu = 0.0;
     if (F32R) {
-      const Arrow1f Q1{(float)P1.b1s, (float)P1.b2s, (float)P1.ab, (float)P1.gb};
-      const Arrow1f Q2{(float)P2.b1s, (float)P2.b2s, (float)P2.ab, (float)P2.gb};
+      const double rab = rcp1(P1.ab);  // both problems share abar
+      const Arrow1f Q1{(float)P1.b1s, (float)P1.b2s, (float)P1.ab, (float)P1.gb,
+                       (float)__builtin_fma(P1.b2s, rab, P1.gb), (float)rab};
+      const Arrow1f Q2{(float)P2.b1s, (float)P2.b2s, (float)P2.ab, (float)P2.gb,
+                       (float)__builtin_fma(P2.b2s, rab, P2.gb), (float)rab};
       // the FP32 problem must be representable away from the poles
       bool fb = !(Q1.b1s >= 0x1p-100f && Q1.b2s >= 0x1p-100f && Q1.ab >= 0x1p-60f);
       float y1 = bg_start32(Q1), y2 = bg_start32(Q2);
@@ -607,8 +619,8 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
         it1 += j1;
         it2 += j2;
       } else if (bad1 || bad2) {
-        // The FP32 zero was too far off for one Newton step (a zero small
-        // next to |gamma_bar|, which FP32 cannot resolve): continue with FP64
+        // The FP32 zero was too far off for one Newton step (rare: a zero
+        // the FP32 arithmetic does not resolve): continue with FP64
         // Borges-Gragg steps.  f is concave, so the Newton iterate lies left
         // of the zero; when it is not positive the FP32 zero was right of it.
         if (bad1 && !(mu > 0.0)) mu = (double)y1;
