@@ -82,12 +82,15 @@ __global__ __launch_bounds__(kBlock) void k_syev3_soa32(uint32_t n, Planes<T> P,
 // AoS: IN = 6 (unique entries) or 9 (full row-major matrix, upper triangle
 // read).  The whole block is read into LDS before any global store, so the
 // full-matrix input may be overwritten by V (in place).  A is therefore not
-// __restrict__.
+// __restrict__.  The outputs leave through the same LDS buffer in two
+// rounds, lambda and then V, so the buffer holds 9 values per matrix rather
+// than 12: 18 KB per workgroup in FP64, which lets 8 waves per SIMD fit in
+// the 160 KB of LDS (24 KB allowed only 6).
 template <typename T, int IN, bool VECS, bool INFO>
 __global__ __launch_bounds__(kBlock) void k_syev3_aos(
     int64_t n, const T* A, T* __restrict__ lam, T* V, uint32_t flags,
     int32_t* __restrict__ info) {
-  __shared__ T sm[kBlock * 12];
+  __shared__ T sm[kBlock * 9];
   const int64_t base = (int64_t)blockIdx.x * kBlock;
   const int cnt = (int)((n - base) < kBlock ? (n - base) : kBlock);
   const int t = threadIdx.x;
@@ -106,22 +109,23 @@ __global__ __launch_bounds__(kBlock) void k_syev3_aos(
     }
   }
   __syncthreads();
+  double l[3], v[9];
   if (t < cnt) {
-    double l[3], v[9];
     const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v);
 #pragma unroll
     for (int j = 0; j < 3; ++j) sm[3 * t + j] = (T)l[j];
-    if (VECS) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) sm[3 * kBlock + 9 * t + k] = (T)v[k];
-    }
     if (INFO) info[base + t] = code;
   }
   __syncthreads();
   for (int k = t; k < cnt * 3; k += kBlock) st_stream(sm[k], lam + base * 3 + k);
   if (VECS) {
-    for (int k = t; k < cnt * 9; k += kBlock)
-      st_stream(sm[3 * kBlock + k], V + base * 9 + k);
+    __syncthreads();  // every lambda read from LDS before V overwrites it
+    if (t < cnt) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sm[9 * t + k] = (T)v[k];
+    }
+    __syncthreads();
+    for (int k = t; k < cnt * 9; k += kBlock) st_stream(sm[k], V + base * 9 + k);
   }
 }
 
