@@ -104,6 +104,20 @@ def pmc_traffic(n, khash):
     return ent.get("hbm_bytes_per_launch")
 
 
+def host_info():
+    """Logical CPUs and CPU model of the host the baseline ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
 def cpu_baseline(torch, gen, target_s):
     """The oracle, as it is, on the host's cores: a fixed sample of the
     headline workload's matrices, solved repeatedly until about target_s
@@ -136,6 +150,7 @@ def cpu_baseline(torch, gen, target_s):
             "sample": f"{m} matrices of the SPD workload's generator (CPU draw, seed 2), "
                       f"FP64 vals+vecs, solved {reps} times in {dt:.1f} s on {threads} "
                       f"threads",
+            "host": host_info(),
             "value_1_core": reps1 * m1 / dt1,
             "sample_1_core": f"the first {m1} of those matrices, solved {reps1} times in "
                              f"{dt1:.1f} s on 1 thread"}
@@ -258,6 +273,7 @@ def main():
                      "kernel": "k_syev3_soa32<double, vecs>",
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "ms_per_launch": ms_launch,
+                     "ms_per_launch_median": sorted(per_ms)[len(per_ms) // 2],
                      "stream_ceiling_GBps": bytes_launch / (ms_ref * 1e-3) / 1e9,
                      "frac_of_stream_ceiling": ms_ref / ms_launch},
         "kernel_hash": khash,
