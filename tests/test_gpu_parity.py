@@ -293,3 +293,39 @@ def test_adjacent_arrays_in_one_buffer_are_accepted(layout):
     else:
         assert torch.equal(buf[6 * n:9 * n].view(n, 3), lam_ref)
         assert torch.equal(buf[9 * n:].view(n, 3, 3), V_ref)
+
+
+def test_64bit_offset_kernel_at_its_size():
+    """n * 8 bytes > 2^32: the SoA kernel with 64-bit offsets, which every
+    smaller batch leaves to the 32-bit-offset kernel.  Its results equal,
+    bitwise, those of the 32-bit-offset kernel on the first 2^28 matrices;
+    every matrix meets the bar by the device measures; a sample meets it
+    against the oracle.  Needs about 120 GB of device memory."""
+    if torch.cuda.get_device_properties(0).total_memory < (160 << 30):
+        pytest.skip("needs about 120 GB of device memory")
+    n = (1 << 29) + 17
+    print(f"64-bit offsets: n={n}", flush=True)
+    A = gen.normal(n, 41, "cuda")
+    lam, V = solve_soa(A)
+    head = 1 << 28
+    Ah = A[:, :head].contiguous()
+    lam_h, V_h = solve_soa(Ah)
+    assert torch.equal(lam[:, :head], lam_h) and torch.equal(V[:, :head], V_h)
+    del Ah, lam_h, V_h
+    torch.cuda.empty_cache()
+    res, orth = device_measures(A, lam, V)
+    rmax = res.max().item() / EPS64
+    omax = orth.max().item() / EPS64
+    print(f"  all {n}: max res {rmax:.2f} eps|A|, max orth {omax:.2f} eps", flush=True)
+    assert rmax <= TOL and omax <= TOL
+    idx = np.concatenate([sample_indices(n, 10_000, 41), np.arange(n - 300, n)])
+    it = torch.from_numpy(idx).cuda()
+    A6 = A[:, it].t().cpu().numpy()
+    lam_s = lam[:, it].t().cpu().numpy()
+    lam_o, _ = oracle.solve(A6)
+    e = checks.eig_error(A6, lam_s, lam_o)
+    print(f"  sample {len(idx)} (with the last 300) vs oracle: max {e.max():.2f} eps|A|",
+          flush=True)
+    assert e.max() <= TOL
+    del A, lam, V, res, orth
+    torch.cuda.empty_cache()
