@@ -145,8 +145,9 @@ int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
  * syev3_stream_reference -- measurement aid, not a solver: reads the 6
  * input planes and writes the 3 + 9 output planes (V may be NULL) exactly
  * as batched_syev3 does in SoA layout with ld = n, with trivial arithmetic
- * in between.  Its bandwidth is the practical HBM ceiling of the solver's
- * memory traffic on the device.  Same argument rules as batched_syev3.
+ * in between, its workgroups in launch order.  A yardstick for the solver's
+ * memory traffic, not a bound: the solver orders its workgroups by XCD for
+ * large batches and can run faster.  Same argument rules as batched_syev3.
  */
 int syev3_stream_reference(int64_t n, const void* A_upper6, void* lambda, void* V,
                            int dtype, hipStream_t stream);
