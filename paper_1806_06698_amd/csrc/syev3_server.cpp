@@ -145,6 +145,7 @@ int syev3_server::launch_tick(int slot) {
   int64_t tiles = 0;
   bool staged_in = false, staged_out = false;
   hipError_t e = hipSuccess;
+  hipEvent_t last_ready = nullptr;
   tk.reqs.clear();
   while (!queue.empty() && nseg < o.max_segments_per_tick) {
     const int ri = queue.front();
@@ -161,7 +162,9 @@ int syev3_server::launch_tick(int slot) {
     tiles += (r.n + syev3::kBlock - 1) / syev3::kBlock;
     r.state = kRunning;
     tk.reqs.push_back(ri);
-    if (r.ready) (void)hipStreamWaitEvent(tk.stream, r.ready, 0);
+    // requests submitted together often share one ready event: wait once
+    if (r.ready && r.ready != last_ready) (void)hipStreamWaitEvent(tk.stream, r.ready, 0);
+    last_ready = r.ready;
     if (r.h_A && e == hipSuccess) {
       const size_t es = r.dtype == SYEV3_F64 ? 8 : 4;
       e = hipMemcpyAsync(r.A, r.h_A, 6 * (size_t)r.n * es, hipMemcpyHostToDevice, tk.copy_in);
@@ -518,6 +521,21 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
   std::memset(out, 0, sizeof(*out));
   hipStream_t prod = nullptr;
   if (hipStreamCreateWithFlags(&prod, hipStreamNonBlocking) != hipSuccess) return SYEV3_E_HIP;
+  // Ready events of submitted groups.  A group's event is recorded again only
+  // after ring.size() = max_requests later groups; those cannot all be
+  // admitted while the group's own requests are still held, so an event is
+  // never re-recorded while a queued request still refers to it.
+  constexpr int kGroup = 64;
+  std::vector<hipEvent_t> ring((size_t)s->o.max_requests, nullptr);
+  size_t ring_next = 0;
+  for (auto& e : ring) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (auto& f : ring)
+        if (f) (void)hipEventDestroy(f);
+      (void)hipStreamDestroy(prod);
+      return SYEV3_E_HIP;
+    }
+  }
   std::mt19937_64 rng(o->seed);
   std::uniform_real_distribution<double> U(0.0, 1.0);
   std::exponential_distribution<double> gap(closed ? 1.0 : o->qps);
@@ -568,9 +586,38 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
         next_t += gap(rng);
       }
     }
-    // admit in arrival order; write the inputs of the whole batch, then
-    // submit it at once
+    // Admit in arrival order.  The inputs of each group of up to kGroup
+    // requests are copied on the producer stream, an event marks the end of
+    // the copies, and the group is submitted with that event as its ready
+    // point: the tick waits for the copies on the device while the host goes
+    // on with the next group, so input copies overlap the solves of ticks
+    // already launched.
     batch.clear();
+    auto flush = [&]() {
+      if (batch.empty() || rc != SYEV3_OK) return;
+      hipEvent_t ev = ring[ring_next];
+      ring_next = (ring_next + 1) % ring.size();
+      if (hipEventRecord(ev, prod) != hipSuccess) {
+        rc = SYEV3_E_HIP;
+        return;
+      }
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const auto ts = Clock::now();
+        for (int64_t id : batch) {
+          int slot;
+          Request* r = lookup(s, id, &slot);
+          if (!r || r->state != kAdmitted) { rc = SYEV3_E_STATE; break; }
+          r->state = kQueued;
+          r->ready = ev;
+          r->t_submit = ts;
+          s->queue.push_back(slot);
+          s->st.submitted++;
+        }
+      }
+      s->cv_sched.notify_one();
+      batch.clear();
+    };
     while (!waiting.empty()) {
       const Arrival& a = waiting.front();
       syev3_request_buffers b;
@@ -590,7 +637,9 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
           break;
         }
       } else {
-        const int64_t off = (int64_t)(U(rng) * (double)(o->src_n - a.n + 1));
+        // a random window of the source pool
+        const int64_t off = std::min<int64_t>(
+            o->src_n - a.n, (int64_t)(U(rng) * (double)(o->src_n - a.n + 1)));
         if (hipMemcpy2DAsync(b.A, (size_t)a.n * es, src + (size_t)off * es,
                              (size_t)o->src_n * es, (size_t)a.n * es, 6,
                              hipMemcpyDeviceToDevice, prod) != hipSuccess) {
@@ -599,33 +648,14 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
           break;
         }
         batch.push_back(id);
+        if ((int)batch.size() == kGroup) flush();
       }
       admit_wait_sum += seconds_since(t0, Clock::now()) - a.t;
       admitted++;
       live[id] = Live{a.t, a.n};
       waiting.pop_front();
     }
-    if (rc == SYEV3_OK && !batch.empty()) {
-      if (hipStreamSynchronize(prod) != hipSuccess) {
-        rc = SYEV3_E_HIP;
-      } else {
-        {
-          std::lock_guard<std::mutex> lk(s->mu);
-          const auto ts = Clock::now();
-          for (int64_t id : batch) {
-            int slot;
-            Request* r = lookup(s, id, &slot);
-            if (!r || r->state != kAdmitted) { rc = SYEV3_E_STATE; break; }
-            r->state = kQueued;
-            r->ready = nullptr;
-            r->t_submit = ts;
-            s->queue.push_back(slot);
-            s->st.submitted++;
-          }
-        }
-        s->cv_sched.notify_one();
-      }
-    }
+    flush();
     if (rc != SYEV3_OK) break;
     // completions
     {
@@ -664,6 +694,7 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
   }
   (void)hipStreamSynchronize(prod);
   (void)hipStreamDestroy(prod);
+  for (auto& e : ring) (void)hipEventDestroy(e);
   if (rc != SYEV3_OK) return rc;
   std::sort(lat.begin(), lat.end());
   auto pct = [&](double q) {
