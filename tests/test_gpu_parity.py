@@ -61,6 +61,19 @@ def test_matches_oracle_every_matrix(kind, n, seed):
     _compare_full(A, label=kind)
 
 
+def test_many_seeds():
+    """Twelve more independent draws of the stress mix, SPD and N(0,1)
+    workloads (seeds not used elsewhere), each matrix against the oracle."""
+    worst = 0.0
+    for seed in range(100, 104):
+        for kind, sd in (("stress_mix", seed), ("spd_fe", seed), ("normal", seed + 50)):
+            # (the stress mix starts from the same N(0,1) draw as "normal")
+            A, _ = gen.make(kind, 65_536 + seed, sd)
+            lam, V = _compare_full(A, label=f"{kind}/seed={seed}")
+            worst = max(worst, checks.orthogonality(V).max())
+    print(f"worst orthogonality over the sweep {worst:.2f} eps", flush=True)
+
+
 @pytest.mark.parametrize("flags,oflags", [
     (s3.FLAG_SIMPLIFIED_DEFLATION, oracle.SIMPLIFIED_DEFLATION),
     (s3.FLAG_NO_H_GUARD, oracle.NO_H_GUARD),
@@ -211,6 +224,23 @@ def test_power_of_two_scaling_bitwise():
         lam, V = solve_soa(torch.ldexp(A, torch.tensor(j)).cuda())
         assert torch.equal(lam, torch.ldexp(lam0, torch.tensor(j, device="cuda")))
         assert torch.equal(V, V0)
+
+
+def test_scaling_to_the_ends_of_the_double_range():
+    """Integer matrices (|a| < 2^13, so exact even as subnormals at 2^-1060)
+    scaled by 2^-1060 (every entry subnormal) and by 2^1000: the solver's own
+    power-of-two scaling sees the same matrix, so V is bitwise unchanged and
+    lambda is the scaled result rounded once (to a subnormal at 2^-1060)."""
+    g = np.random.default_rng(37)
+    A6 = g.integers(-4000, 4001, size=(50_000, 6)).astype(np.float64)
+    lam0, V0 = solve_soa(torch.from_numpy(A6.T.copy()).cuda())
+    for j in (-1060, 1000):
+        As6 = np.ldexp(A6, j)
+        assert np.array_equal(np.ldexp(As6, -j), A6)               # exact
+        lam, V = solve_soa(torch.from_numpy(As6.T.copy()).cuda())
+        assert torch.equal(V, V0), j
+        expect = torch.from_numpy(np.ldexp(lam0.cpu().numpy(), j)).cuda()
+        assert torch.equal(lam, expect), j
 
 
 # --------------------------------------------------------------------------
