@@ -359,3 +359,34 @@ def test_64bit_offset_kernel_at_its_size():
     assert e.max() <= TOL
     del A, lam, V, res, orth
     torch.cuda.empty_cache()
+
+
+def test_capture_in_a_hip_graph_and_replay():
+    """The batched entry point only enqueues a kernel (no allocation, no
+    host synchronisation), so it can be captured in a HIP graph.  Each
+    replay, with new input copied in and other eager work and a
+    synchronisation between replays, must match an eager solve bitwise."""
+    n = 100_003
+    A = torch.empty((6, n), dtype=torch.float64, device="cuda")
+    lam = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    V = torch.empty((9, n), dtype=torch.float64, device="cuda")
+    A.copy_(gen.normal(n, 50).cuda())
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):                 # warm-up outside the capture
+        s3.syev3(A, out=(lam, V))
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        s3.syev3(A, out=(lam, V))
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for k in range(5):
+        A.copy_(gen.make(("stress_mix", "spd_fe", "normal")[k % 3], n, 60 + k)[0].cuda())
+        g.replay()
+        scratch.add_(1.0).mul_(0.5)           # eager work between replays
+        torch.cuda.synchronize()
+        lam_e, V_e = s3.syev3(A.clone())
+        torch.cuda.synchronize()
+        assert torch.equal(lam, lam_e) and torch.equal(V, V_e), f"replay {k}"
