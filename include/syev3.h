@@ -207,6 +207,8 @@ typedef struct {
   int32_t inflight_ticks_peak;
   int32_t segments_per_tick_peak;
   double busy_seconds;         /* wall time with at least one tick on the GPU */
+  int64_t queue_depth;         /* requests submitted and not yet in a tick */
+  int64_t queue_depth_peak;
 } syev3_server_stats;
 
 /* Defaults: 64 GiB pool, 4096 slots, 4 ticks in flight, 256 segments/tick,

@@ -62,7 +62,9 @@ class ServerStats(ctypes.Structure):
                 ("acquire_rejections", ctypes.c_int64),
                 ("inflight_ticks_peak", ctypes.c_int32),
                 ("segments_per_tick_peak", ctypes.c_int32),
-                ("busy_seconds", ctypes.c_double)]
+                ("busy_seconds", ctypes.c_double),
+                ("queue_depth", ctypes.c_int64),
+                ("queue_depth_peak", ctypes.c_int64)]
 
 
 def lib() -> ctypes.CDLL:

@@ -64,7 +64,9 @@ def build(verbose: bool = False) -> str:
                 sys.stderr.write(p.stderr)
             objs.append(obj)
         out_tmp = LIB + ".tmp"
+        rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(cc))), "lib")
         cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs,
+               "-L" + rocm_lib, "-Wl,-rpath," + rocm_lib, "-lrocprofiler-sdk-roctx",
                "-lpthread"]
         if verbose:
             print(" ".join(cmd), flush=True)

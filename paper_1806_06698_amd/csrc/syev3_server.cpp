@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -30,6 +31,8 @@
 #include <random>
 #include <thread>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "syev3.h"
 #include "syev3_internal.hpp"
@@ -81,6 +84,9 @@ struct TickSlot {
   hipGraphExec_t exec = nullptr;
   std::vector<int> reqs;
   bool busy = false;
+  // a profiler range from launch to observed completion
+  // (rocprofv3 --marker-trace shows the ticks in flight)
+  roctx_range_id_t range = 0;
 };
 
 }  // namespace
@@ -112,6 +118,10 @@ struct syev3_server {
 
   void scheduler();
   int launch_tick(int slot);
+  // after every push onto the queue (mu held)
+  void note_queue() {
+    st.queue_depth_peak = std::max<int64_t>(st.queue_depth_peak, (int64_t)queue.size());
+  }
 };
 
 namespace {
@@ -205,6 +215,10 @@ int syev3_server::launch_tick(int slot) {
     e = hipEventRecord(tk.done, tk.stream);
   }
   if (e != hipSuccess) return SYEV3_E_HIP;
+  char label[64];
+  std::snprintf(label, sizeof label, "syev3 tick: %d requests, %lld tiles", nseg,
+                (long long)tiles);
+  tk.range = roctxRangeStartA(label);
   tk.busy = true;
   if (busy_ticks++ == 0) busy_since = Clock::now();
   st.ticks++;
@@ -235,6 +249,7 @@ void syev3_server::scheduler() {
       }
       tk.reqs.clear();
       tk.busy = false;
+      roctxRangeStop(tk.range);
       if (--busy_ticks == 0) st.busy_seconds += seconds_since(busy_since, now);
       any_done = true;
     }
@@ -428,6 +443,7 @@ int syev3_server_submit(syev3_server* s, int64_t id, hipEvent_t ready) {
     r->ready = ready;
     r->t_submit = Clock::now();
     s->queue.push_back(slot);
+    s->note_queue();
     s->st.submitted++;
   }
   s->cv_sched.notify_one();
@@ -450,6 +466,7 @@ int syev3_server_submit_host(syev3_server* s, int64_t id, const void* host_A,
     r->h_V = r->vecs ? host_V : nullptr;
     r->t_submit = Clock::now();
     s->queue.push_back(slot);
+    s->note_queue();
     s->st.submitted++;
   }
   s->cv_sched.notify_one();
@@ -506,6 +523,7 @@ int syev3_server_get_stats(syev3_server* s, syev3_server_stats* out) {
   if (!s || !out) return SYEV3_E_NULL;
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->st;
+  out->queue_depth = (int64_t)s->queue.size();
   if (s->busy_ticks > 0) out->busy_seconds += seconds_since(s->busy_since, Clock::now());
   return SYEV3_OK;
 }
@@ -612,6 +630,7 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
           r->ready = ev;
           r->t_submit = ts;
           s->queue.push_back(slot);
+          s->note_queue();
           s->st.submitted++;
         }
       }

@@ -74,6 +74,7 @@ def test_each_result_same_alone_and_in_the_mix(source, use_graphs):
         st = srv.stats()
         assert st["completed"] == len(sizes)
         assert st["pool_bytes_in_use"] == 0
+        assert st["queue_depth"] == 0 and 1 <= st["queue_depth_peak"] <= len(sizes)
 
 
 def test_many_ticks_with_eager_work_between_replays(source):
