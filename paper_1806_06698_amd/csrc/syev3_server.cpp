@@ -215,10 +215,7 @@ int syev3_server::launch_tick(int slot) {
     e = hipEventRecord(tk.done, tk.stream);
   }
   if (e != hipSuccess) return SYEV3_E_HIP;
-  char label[64];
-  std::snprintf(label, sizeof label, "syev3 tick: %d requests, %lld tiles", nseg,
-                (long long)tiles);
-  tk.range = roctxRangeStartA(label);
+  tk.range = roctxRangeStartA("syev3 tick");
   tk.busy = true;
   if (busy_ticks++ == 0) busy_since = Clock::now();
   st.ticks++;
