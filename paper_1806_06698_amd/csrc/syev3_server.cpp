@@ -22,7 +22,6 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
-#include <cstdio>
 #include <cstring>
 #include <deque>
 #include <map>
