@@ -390,3 +390,31 @@ def test_capture_in_a_hip_graph_and_replay():
         lam_e, V_e = s3.syev3(A.clone())
         torch.cuda.synchronize()
         assert torch.equal(lam, lam_e) and torch.equal(V, V_e), f"replay {k}"
+
+
+@pytest.mark.parametrize("dtype,layout", [(s3.F64, s3.AOS), (s3.F64, s3.AOS9),
+                                          (s3.F32_REFINE, s3.AOS), (s3.F32_REFINE, s3.AOS9)])
+def test_aos_arrays_not_16_byte_aligned(dtype, layout):
+    """AoS arrays one element into a buffer (aligned to their element, not to
+    16 bytes) take the element-wide copies through LDS; an odd count puts a
+    partial block at the end.  Results equal the aligned call's bitwise."""
+    n = 3 * 256 + 37
+    A, _ = gen.make("stress_mix", n, 70)
+    tdt = torch.float64 if dtype == s3.F64 else torch.float32
+    width = 6 if layout == s3.AOS else 9
+    Aa = gen.to_aos(A) if width == 6 else gen.to_full(A).reshape(n, 9)
+    Aa = Aa.to(tdt).cuda().contiguous()
+    lam_ref, V_ref = s3.syev3(Aa, layout="aos" if width == 6 else "aos9")
+    es = Aa.element_size()
+    buf = torch.empty(width * n + 1, dtype=tdt, device="cuda")
+    buf[1:].copy_(Aa.reshape(-1))
+    lbuf = torch.full((3 * n + 1,), float("nan"), dtype=tdt, device="cuda")
+    vbuf = torch.full((9 * n + 1,), float("nan"), dtype=tdt, device="cuda")
+    assert (buf.data_ptr() + es) % 16 != 0
+    rc = s3.batched_syev3_ex(n, buf.data_ptr() + es, 0, layout, lbuf.data_ptr() + es,
+                             vbuf.data_ptr() + es, dtype, 0,
+                             torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert rc == 0
+    assert torch.equal(lbuf[1:].view(n, 3), lam_ref)
+    assert torch.equal(vbuf[1:].view(n, 3, 3), V_ref)
