@@ -88,7 +88,13 @@ extern "C" {
 #define SYEV3_FLAG_NEWTON 4u      /* Newton's method from the left
                                      (Sec. 1.4.2) instead of Borges-Gragg;
                                      SYEV3_F64 only */
-#define SYEV3_FLAGS_ALL 7u
+#define SYEV3_FLAG_PAPER_BG 8u    /* Borges-Gragg exactly as Sec. 1.4.1
+                                     states it: start from the first iterate
+                                     from +infinity, stop when f/f' < 2 eps x.
+                                     For measuring what the default start
+                                     and stop test save; SYEV3_F64 only, not
+                                     with SYEV3_FLAG_NEWTON */
+#define SYEV3_FLAGS_ALL 15u
 
 /* error codes */
 #define SYEV3_OK 0

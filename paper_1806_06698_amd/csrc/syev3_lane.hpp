@@ -47,6 +47,7 @@ constexpr int kMaxIter32 = 24;   // FP32 zero-finder evaluations per root
 constexpr uint32_t kFlagSimplified = 1u;
 constexpr uint32_t kFlagNoHGuard = 2u;
 constexpr uint32_t kFlagNewton = 4u;
+constexpr uint32_t kFlagPaperBG = 8u;
 // internal: FP32 zero finder without the FP64 Newton step and without the
 // re-orthogonalisation (an ablation of the refinement); never set by callers
 constexpr uint32_t kFlagUnrefined = 1u << 31;
@@ -317,8 +318,8 @@ __device__ __forceinline__ double start_point(const Arrow1& P, double rab) {
 //    not move x towards the zero (rounding at the zero) stops with x.
 // D is computed to about 2^-46: near the zero a cubic step's own error must
 // stay below the rounding level.
-__device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop) {
-  const Spec s = spec_eval(P, x);
+__device__ __forceinline__ double bg_update(const Arrow1& P, double x, const Spec& s,
+                                            bool& stop) {
   const bool left = s.f < 0.0;
   const double w0m1 = (s.q2 * P.ab) * (s.rp * s.rp);
   const double w0 = w0m1 + 1.0;
@@ -346,6 +347,28 @@ __device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop)
   const double D = dabs(x - xn);
   if (w0m1 * (D * D) * D <= 2.0 * kEps64 * (xn * xn) * (xn + P.ab) * (left ? 1.0 : s.fp))
     stop = true;
+  return xn;
+}
+
+__device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop) {
+  return bg_update(P, x, spec_eval(P, x), stop);
+}
+
+// Borges-Gragg as the paper states it, for measuring what the start and the
+// stop test above save (flag kFlagPaperBG): the start is x_inf, the first
+// iterate from +infinity (Sec. 1.4.1); before each step the iteration stops
+// when f/f' < 2 eps x (the paper's test with C = 2), when rounding has
+// reached the zero (f <= 0), or when the step no longer decreases x.  Each
+// step is bg_step's from the right; its own stop bound is not used.
+__device__ __forceinline__ double paper_step(const Arrow1& P, double x, bool& stop) {
+  const Spec s = spec_eval(P, x);
+  if (!(s.f > 0.0) || s.f < 2.0 * kEps64 * x * s.fp) {
+    stop = true;
+    return x;
+  }
+  bool unused = false;
+  const double xn = bg_update(P, x, s, unused);
+  if (!(xn < x)) stop = true;
   return xn;
 }
 
@@ -385,6 +408,20 @@ __device__ __forceinline__ void zeros_bg(const Arrow1& P1, const Arrow1& P2,
     if (s1 && s2) break;
     if (!s1) { ++it1; x1 = bg_step(P1, x1, s1); }
     if (!s2) { ++it2; x2 = bg_step(P2, x2, s2); }
+  }
+}
+
+__device__ __forceinline__ void zeros_bg_paper(const Arrow1& P1, const Arrow1& P2,
+                                               double& x1, double& x2, int& it1, int& it2) {
+  x1 = quad_zero(P1.gb, P1.b1s + P1.b2s, 1.0);
+  x2 = quad_zero(P2.gb, P2.b1s + P2.b2s, 1.0);
+  bool s1 = false, s2 = false;
+  it1 = 0;
+  it2 = 0;
+  for (int k = 0; k < 2 * kMaxIter; ++k) {
+    if (s1 && s2) break;
+    if (!s1) { ++it1; x1 = paper_step(P1, x1, s1); }
+    if (!s2) { ++it2; x2 = paper_step(P2, x2, s2); }
   }
 }
 
@@ -634,6 +671,8 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
       }
     } else if (flags & kFlagNewton) {
       zeros_newton(P1, P2, mu, nu, it1, it2);
+    } else if (flags & kFlagPaperBG) {
+      zeros_bg_paper(P1, P2, mu, nu, it1, it2);
     } else {
       zeros_bg(P1, P2, mu, nu, it1, it2);
     }

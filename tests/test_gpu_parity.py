@@ -78,11 +78,39 @@ def test_many_seeds():
     (s3.FLAG_SIMPLIFIED_DEFLATION, oracle.SIMPLIFIED_DEFLATION),
     (s3.FLAG_NO_H_GUARD, oracle.NO_H_GUARD),
     (s3.FLAG_NEWTON, oracle.NEWTON),
+    (s3.FLAG_PAPER_BG, 0),                 # the oracle's zero finder is the paper's
 ])
 def test_flag_variants(flags, oflags):
     for kind, seed in (("normal", 20), ("spd_fe", 21), ("uniform", 22)):
         A, _ = gen.make(kind, 40_000, seed, "cpu")
         _compare_full(A, flags=flags, oflags=oflags, label=f"{kind}/flags={flags}")
+
+
+def test_paper_zero_finder_takes_the_oracles_steps():
+    """With FLAG_PAPER_BG the GPU runs the paper's start and stop test, as
+    the oracle does: the number of evaluations per root matches the
+    oracle's on at least 95% of the roots and has the same mean to two
+    digits, meets the bar on the stress mix, and averages several times the
+    default zero finder's count.  (The two evaluate f with different
+    division sequences and test f < 2 eps x f' against f/f' < 2 eps x, so a
+    stop within rounding of the threshold can fall one evaluation apart;
+    97.6% agree on this input.)"""
+    A, _ = gen.stress_mix(100_000, 33, "cpu")
+    lam, V = _compare_full(A, flags=s3.FLAG_PAPER_BG, oflags=0, label="paper BG/stress")
+    _, _, info = solve_soa(A.cuda(), flags=s3.FLAG_PAPER_BG, info=True)
+    _, _, info_d = solve_soa(A.cuda(), info=True)
+    info, info_d = info.cpu().numpy(), info_d.cpu().numpy()
+    _, _, oinfo = oracle.solve(gen.to_aos(A).numpy(), return_info=True)
+    red = ((info & 0xFF) == 4) & (oinfo[:, 0] == 4)
+    it = np.stack([(info >> 8) & 0xFF, (info >> 16) & 0xFF], 1)[red]
+    it_o = oinfo[red][:, 1:3]
+    it_d = np.stack([(info_d >> 8) & 0xFF, (info_d >> 16) & 0xFF], 1)[red]
+    agree = np.mean(it == it_o)
+    print(f"evaluations per root: paper BG {it.mean():.2f}, oracle {it_o.mean():.2f}, "
+          f"default {it_d.mean():.2f}; per-root agreement with the oracle {agree:.4f}",
+          flush=True)
+    assert agree > 0.95 and abs(it.mean() - it_o.mean()) < 0.01
+    assert it.mean() > 2.0 * it_d.mean()
 
 
 def test_newton_on_stress_mix():
