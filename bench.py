@@ -186,10 +186,10 @@ def f32r_errors(torch, gen, s3, n_sample=200_000, refine=True):
                                  "on lambda_min are not resolvable"}
 
 
-def zero_finder_stats(torch, s3, A):
+def zero_finder_stats(torch, s3, A, flags=0):
     """Branches and zero-finder evaluations on the headline workload, from
     one untimed launch that also writes the per-matrix info word."""
-    _, _, info = s3.syev3(A, info=True)
+    _, _, info = s3.syev3(A, info=True, flags=flags)
     br = info & 0xFF
     it = torch.stack([(info >> 8) & 0xFF, (info >> 16) & 0xFF])
     red = br == 4
@@ -236,8 +236,9 @@ def main():
     total_s, per_ms, span_s = timed_launches(step, args.steps, args.warmup, torch)
     ms_launch = sum(per_ms) / len(per_ms)
 
-    # the same loads and stores with the solve taken out: the practical HBM
-    # ceiling of this traffic on this device
+    # the same loads and stores with the solve taken out, in launch order: a
+    # yardstick for this traffic on this device (the solver's workgroup order
+    # can overlap it better, so it is not a bound)
     from paper_1806_06698_amd import _lib
     sh = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -282,18 +283,21 @@ def main():
         "kernel_hash": khash,
     }
     line["zero_finder"] = zero_finder_stats(torch, s3, A)
+    if not args.headline_only:
+        line["zero_finder_paper_bg"] = zero_finder_stats(torch, s3, A, flags=s3.FLAG_PAPER_BG)
     del A, lam, V
     torch.cuda.empty_cache()
 
     if not args.headline_only:
         side = {}
 
-        def run_variant(name, A, layout, vectors, dtype_key, steps=10):
+        def run_variant(name, A, layout, vectors, dtype_key, steps=10, flags=0):
             nn = A.shape[1] if layout == "soa" else A.shape[0]
             refine = dtype_key != "f32"
-            out = s3.syev3(A, layout=layout, vectors=vectors, refine=refine)
+            out = s3.syev3(A, layout=layout, vectors=vectors, refine=refine, flags=flags)
             torch.cuda.synchronize()
-            fn = (lambda: s3.syev3(A, layout=layout, vectors=vectors, out=out, refine=refine))
+            fn = (lambda: s3.syev3(A, layout=layout, vectors=vectors, out=out, refine=refine,
+                                   flags=flags))
             _, per, span = timed_launches(fn, steps, 5, torch)  # 5 warm-up launches
             msl = sum(per) / len(per)
             b = BYTES_PER_MATRIX[(dtype_key, vectors)] * nn
@@ -307,6 +311,13 @@ def main():
         run_variant("spd_fe_64m_f32r_soa", Af, "soa", True, "f32r")
         run_variant("spd_fe_64m_f32_unrefined_soa", Af, "soa", True, "f32")
         run_variant("spd_fe_64m_f64_soa_valsonly", A, "soa", False, "f64")
+        # Zero-finder ablations on the headline workload: the paper's own
+        # Borges-Gragg iteration (start and stop as Sec. 1.4 gives them) and
+        # Newton's method from the left (Sec. 1.4.2).
+        run_variant("spd_fe_64m_f64_soa_paper_bg", A, "soa", True, "f64",
+                    flags=s3.FLAG_PAPER_BG)
+        run_variant("spd_fe_64m_f64_soa_newton", A, "soa", True, "f64",
+                    flags=s3.FLAG_NEWTON)
         Aa = A.t().contiguous()
         run_variant("spd_fe_64m_f64_aos", Aa, "aos", True, "f64")
         del Aa, Af
