@@ -110,6 +110,7 @@ extern "C" {
 #define SYEV3_E_AGAIN (-9)    /* server: no room now; retry after a release */
 #define SYEV3_E_STATE (-10)   /* server: bad handle or request state */
 #define SYEV3_E_TIMEOUT (-11) /* server: wait timed out */
+#define SYEV3_E_NOMEM (-12)   /* server: host memory could not be allocated */
 
 /*
  * batched_syev3 -- eigenvalues (and eigenvectors if V != NULL) of n
@@ -188,11 +189,18 @@ int syev3_version(void);
  */
 typedef struct syev3_server syev3_server;
 
+/* Largest accepted syev3_server_opts.max_requests. */
+#define SYEV3_SERVER_MAX_REQUESTS 65536
+/* Largest accepted syev3_server_opts.max_segments_per_tick. */
+#define SYEV3_SERVER_MAX_SEGMENTS 1024
+
 typedef struct {
-  uint64_t hbm_budget_bytes;   /* device pool size (request buffers) */
-  int32_t max_requests;        /* request slots (admitted, not released) */
-  int32_t max_inflight_ticks;  /* ticks on the GPU at once (streams) */
-  int32_t max_segments_per_tick; /* requests per tick */
+  uint64_t hbm_budget_bytes;   /* device pool size (request buffers), >= 256 */
+  int32_t max_requests;        /* request slots (admitted, not released),
+                                  1 .. SYEV3_SERVER_MAX_REQUESTS */
+  int32_t max_inflight_ticks;  /* ticks on the GPU at once (streams), 1 .. 64 */
+  int32_t max_segments_per_tick; /* requests per tick,
+                                    1 .. SYEV3_SERVER_MAX_SEGMENTS */
   int32_t grid_blocks;         /* blocks of the persistent kernel; 0 = auto */
   int32_t use_graphs;          /* 1: launch ticks through captured graphs */
 } syev3_server_opts;
@@ -222,7 +230,10 @@ typedef struct {
 void syev3_server_default_opts(syev3_server_opts* opts);
 
 /* Create a server on the current device.  Allocates the pool and starts the
- * scheduler thread.  *out receives the handle. */
+ * scheduler thread.  *out receives the handle (NULL on failure).  Returns
+ * SYEV3_E_N for an option outside its range, SYEV3_E_BUDGET if the pool
+ * cannot be allocated on the device, SYEV3_E_NOMEM if host memory runs out,
+ * SYEV3_E_HIP for another HIP failure (streams, events, graphs). */
 int syev3_server_create(const syev3_server_opts* opts, syev3_server** out);
 
 /* Stop the scheduler (after in-flight ticks finish) and free everything. */

@@ -25,7 +25,7 @@ FLAG_PAPER_BG = 8
 E = {
     0: "OK", -1: "E_N", -2: "E_NULL", -3: "E_DTYPE", -4: "E_LAYOUT",
     -5: "E_ALIAS", -6: "E_HIP", -7: "E_FLAGS", -8: "E_BUDGET", -9: "E_AGAIN",
-    -10: "E_STATE", -11: "E_TIMEOUT",
+    -10: "E_STATE", -11: "E_TIMEOUT", -12: "E_NOMEM",
 }
 E_AGAIN = -9
 

@@ -126,6 +126,7 @@ const char* syev3_strerror(int code) {
     case SYEV3_E_AGAIN: return "server full; retry after a release";
     case SYEV3_E_STATE: return "invalid server handle or request state";
     case SYEV3_E_TIMEOUT: return "timed out waiting for the request";
+    case SYEV3_E_NOMEM: return "server: out of host memory";
     default: return "unknown error code";
   }
 }

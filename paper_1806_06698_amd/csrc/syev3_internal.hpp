@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "syev3.h"
+
 namespace syev3 {
 
 constexpr int kBlock = 256;  // lanes (matrices) per workgroup: 4 wavefronts
@@ -35,7 +37,7 @@ hipError_t launch_stream_reference(int64_t n, const void* A, void* lambda, void*
 
 // A tick's table in device memory: header, then the segments in ascending
 // tile_begin order.  Sized for kMaxSegmentsPerTick; only nseg are read.
-constexpr int kMaxSegmentsPerTick = 1024;
+constexpr int kMaxSegmentsPerTick = SYEV3_SERVER_MAX_SEGMENTS;
 struct TickTable {
   int32_t nseg;
   int32_t reserved;

@@ -27,6 +27,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <system_error>
 #include <random>
 #include <thread>
 #include <vector>
@@ -115,6 +116,7 @@ struct syev3_server {
   Clock::time_point busy_since;
   Clock::time_point t0 = Clock::now();
 
+  int init(const syev3_server_opts& opts);
   void scheduler();
   int launch_tick(int slot);
   // after every push onto the queue (mu held)
@@ -253,7 +255,13 @@ void syev3_server::scheduler() {
     for (int k = 0; k < (int)ticks.size() && !queue.empty(); ++k) {
       if (!ticks[k].busy) {
         if (launch_tick(k) != SYEV3_OK) {
-          // the tick's requests complete as failed; the slot stays idle
+          // The tick's requests complete as failed; the slot stays idle.
+          // Copies enqueued before the failure may still write into their
+          // buffers: let them finish before the buffers can be released.
+          TickSlot& tk = ticks[k];
+          (void)hipStreamSynchronize(tk.copy_in);
+          (void)hipStreamSynchronize(tk.stream);
+          (void)hipStreamSynchronize(tk.copy_out);
           const auto now = Clock::now();
           for (int ri : ticks[k].reqs) {
             req[ri].state = kDone;
@@ -280,6 +288,54 @@ void syev3_server::scheduler() {
   }
 }
 
+// Allocates everything and starts the scheduler; on failure the caller
+// frees what was made with syev3_server_destroy.  Every vector the scheduler
+// thread appends to is reserved here, so that thread never allocates.
+int syev3_server::init(const syev3_server_opts& opts) {
+  o = opts;
+  if (hipGetDevice(&device) != hipSuccess) return SYEV3_E_HIP;
+  if (hipMalloc((void**)&pool, o.hbm_budget_bytes) != hipSuccess) {
+    pool = nullptr;
+    return SYEV3_E_BUDGET;
+  }
+  alloc = new syev3::PoolAllocator(o.hbm_budget_bytes);
+  req.resize(o.max_requests);
+  free_slots.reserve(o.max_requests);
+  for (int k = o.max_requests - 1; k >= 0; --k) free_slots.push_back(k);
+  done_ids.reserve(o.max_requests);
+  table_bytes = syev3::tick_table_bytes(o.max_segments_per_tick);
+  grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : syev3::device_cu_count() * 8;
+  ticks.resize(o.max_inflight_ticks);
+  for (auto& tk : ticks) {
+    tk.reqs.reserve(o.max_segments_per_tick);
+    if (hipStreamCreateWithFlags(&tk.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&tk.copy_in, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&tk.copy_out, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&tk.in_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&tk.kernel_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&tk.done, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void**)&tk.h_table, table_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&tk.d_table, table_bytes) != hipSuccess)
+      return SYEV3_E_HIP;
+    std::memset(tk.h_table, 0, table_bytes);
+    if (o.use_graphs) {
+      // capture: table copy, then the segment kernel; replayed per tick
+      bool ok = hipStreamBeginCapture(tk.stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (ok) {
+        ok = hipMemcpyAsync(tk.d_table, tk.h_table, table_bytes, hipMemcpyHostToDevice,
+                            tk.stream) == hipSuccess;
+        ok = ok && syev3::launch_segments(tk.d_table, grid_blocks, tk.stream) == hipSuccess;
+        const bool ended = hipStreamEndCapture(tk.stream, &tk.graph) == hipSuccess;
+        ok = ok && ended;
+      }
+      ok = ok && hipGraphInstantiate(&tk.exec, tk.graph, nullptr, nullptr, 0) == hipSuccess;
+      if (!ok) return SYEV3_E_HIP;
+    }
+  }
+  thr = std::thread([this] { scheduler(); });
+  return SYEV3_OK;
+}
+
 extern "C" {
 
 void syev3_server_default_opts(syev3_server_opts* o) {
@@ -298,58 +354,25 @@ int syev3_server_create(const syev3_server_opts* opts, syev3_server** out) {
   syev3_server_opts o;
   syev3_server_default_opts(&o);
   if (opts) o = *opts;
-  if (o.hbm_budget_bytes < kAlign || o.max_requests < 1 || o.max_inflight_ticks < 1 ||
+  if (o.hbm_budget_bytes < kAlign || o.max_requests < 1 ||
+      o.max_requests > SYEV3_SERVER_MAX_REQUESTS || o.max_inflight_ticks < 1 ||
       o.max_inflight_ticks > 64 || o.max_segments_per_tick < 1 ||
       o.max_segments_per_tick > syev3::kMaxSegmentsPerTick || o.grid_blocks < 0)
     return SYEV3_E_N;
-  syev3_server* s = new (std::nothrow) syev3_server();
-  if (!s) return SYEV3_E_HIP;
-  s->o = o;
+  syev3_server* s = nullptr;
   int rc = SYEV3_OK;
-  if (hipGetDevice(&s->device) != hipSuccess) rc = SYEV3_E_HIP;
-  if (rc == SYEV3_OK && hipMalloc((void**)&s->pool, o.hbm_budget_bytes) != hipSuccess) {
-    s->pool = nullptr;
-    rc = SYEV3_E_BUDGET;
-  }
-  s->alloc = new syev3::PoolAllocator(o.hbm_budget_bytes);
-  s->req.resize(o.max_requests);
-  for (int k = o.max_requests - 1; k >= 0; --k) s->free_slots.push_back(k);
-  s->table_bytes = syev3::tick_table_bytes(o.max_segments_per_tick);
-  s->grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : syev3::device_cu_count() * 8;
-  s->ticks.resize(o.max_inflight_ticks);
-  for (auto& tk : s->ticks) {
-    if (rc != SYEV3_OK) break;
-    if (hipStreamCreateWithFlags(&tk.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&tk.copy_in, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&tk.copy_out, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&tk.in_done, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&tk.kernel_done, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&tk.done, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void**)&tk.h_table, s->table_bytes, hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&tk.d_table, s->table_bytes) != hipSuccess) {
-      rc = SYEV3_E_HIP;
-      break;
-    }
-    std::memset(tk.h_table, 0, s->table_bytes);
-    if (o.use_graphs) {
-      // capture: table copy, then the segment kernel; replayed per tick
-      bool ok = hipStreamBeginCapture(tk.stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-      if (ok) {
-        ok = hipMemcpyAsync(tk.d_table, tk.h_table, s->table_bytes, hipMemcpyHostToDevice,
-                            tk.stream) == hipSuccess;
-        ok = ok && syev3::launch_segments(tk.d_table, s->grid_blocks, tk.stream) == hipSuccess;
-        const bool ended = hipStreamEndCapture(tk.stream, &tk.graph) == hipSuccess;
-        ok = ok && ended;
-      }
-      ok = ok && hipGraphInstantiate(&tk.exec, tk.graph, nullptr, nullptr, 0) == hipSuccess;
-      if (!ok) rc = SYEV3_E_HIP;
-    }
+  try {
+    s = new syev3_server();
+    rc = s->init(o);
+  } catch (const std::bad_alloc&) {
+    rc = SYEV3_E_NOMEM;
+  } catch (const std::system_error&) {  // the scheduler thread could not start
+    rc = SYEV3_E_NOMEM;
   }
   if (rc != SYEV3_OK) {
-    syev3_server_destroy(s);
+    if (s) syev3_server_destroy(s);
     return rc;
   }
-  s->thr = std::thread([s] { s->scheduler(); });
   *out = s;
   return SYEV3_OK;
 }
@@ -435,10 +458,14 @@ int syev3_server_submit(syev3_server* s, int64_t id, hipEvent_t ready) {
     int slot;
     Request* r = lookup(s, id, &slot);
     if (!r || r->state != kAdmitted) return SYEV3_E_STATE;
+    try {
+      s->queue.push_back(slot);
+    } catch (const std::bad_alloc&) {
+      return SYEV3_E_NOMEM;  // still admitted
+    }
     r->state = kQueued;
     r->ready = ready;
     r->t_submit = Clock::now();
-    s->queue.push_back(slot);
     s->note_queue();
     s->st.submitted++;
   }
@@ -455,13 +482,17 @@ int syev3_server_submit_host(syev3_server* s, int64_t id, const void* host_A,
     int slot;
     Request* r = lookup(s, id, &slot);
     if (!r || r->state != kAdmitted) return SYEV3_E_STATE;
+    try {
+      s->queue.push_back(slot);
+    } catch (const std::bad_alloc&) {
+      return SYEV3_E_NOMEM;  // still admitted
+    }
     r->state = kQueued;
     r->ready = nullptr;
     r->h_A = host_A;
     r->h_lam = host_lambda;
     r->h_V = r->vecs ? host_V : nullptr;
     r->t_submit = Clock::now();
-    s->queue.push_back(slot);
     s->note_queue();
     s->st.submitted++;
   }
@@ -533,6 +564,16 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
       (o->host_staged && (!o->sink || std::exp2(o->max_log2_n) > (double)o->src_n)))
     return SYEV3_E_N;
   std::memset(out, 0, sizeof(*out));
+  // the ready-event ring and the completion list are made before anything
+  // needs undoing
+  std::vector<hipEvent_t> ring;
+  std::vector<int64_t> done;
+  try {
+    ring.assign((size_t)s->o.max_requests, nullptr);
+    done.reserve((size_t)s->o.max_requests);
+  } catch (const std::bad_alloc&) {
+    return SYEV3_E_NOMEM;
+  }
   hipStream_t prod = nullptr;
   if (hipStreamCreateWithFlags(&prod, hipStreamNonBlocking) != hipSuccess) return SYEV3_E_HIP;
   // Ready events of submitted groups.  A group's event is recorded again only
@@ -540,7 +581,6 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
   // admitted while the group's own requests are still held, so an event is
   // never re-recorded while a queued request still refers to it.
   constexpr int kGroup = 64;
-  std::vector<hipEvent_t> ring((size_t)s->o.max_requests, nullptr);
   size_t ring_next = 0;
   for (auto& e : ring) {
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
@@ -562,10 +602,8 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
     double t_arrival;
     int64_t n;
   };
-  std::deque<Arrival> waiting;
   std::map<int64_t, Live> live;
   std::vector<double> lat;
-  std::vector<int64_t> batch, done;
   double admit_wait_sum = 0.0;
   int64_t admitted = 0;
   syev3_server_stats st0{};
@@ -579,6 +617,12 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
   double next_t = closed ? 0.0 : gap(rng);
   double last_done = 0.0;
   int rc = SYEV3_OK;
+  // Host allocations below (the arrival queue, the live map, the latency
+  // list) can fail; that ends the run like any other error, and the drain
+  // and cleanup after the loop allocate nothing.
+  try {
+  std::deque<Arrival> waiting;
+  std::vector<int64_t> batch;
   auto draw = [&](double t) {
     Arrival a;
     a.t = t;
@@ -634,11 +678,21 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
       batch.clear();
     };
     while (!waiting.empty()) {
-      const Arrival& a = waiting.front();
+      const Arrival a = waiting.front();
       syev3_request_buffers b;
       const int64_t id = syev3_server_acquire(s, a.n, a.dtype, o->want_vectors, &b);
       if (id == SYEV3_E_AGAIN) break;
       if (id < 0) { rc = (int)id; break; }
+      waiting.pop_front();
+      // tracked from here on: on any error below the drain releases it
+      try {
+        live[id] = Live{a.t, a.n};
+      } catch (const std::bad_alloc&) {
+        (void)syev3_server_release(s, id);
+        throw;
+      }
+      admit_wait_sum += seconds_since(t0, Clock::now()) - a.t;
+      admitted++;
       const size_t es = a.dtype == SYEV3_F64 ? 8 : 4;
       const char* src = (const char*)(a.dtype == SYEV3_F64 ? o->src_f64 : o->src_f32);
       if (o->host_staged) {
@@ -647,10 +701,7 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
         char* sink = (char*)o->sink;
         rc = syev3_server_submit_host(s, id, src, sink,
                                       o->want_vectors ? sink + 3 * (size_t)a.n * es : nullptr);
-        if (rc != SYEV3_OK) {
-          (void)syev3_server_release(s, id);  // still admitted: give its memory back
-          break;
-        }
+        if (rc != SYEV3_OK) break;
       } else {
         // a random window of the source pool
         const int64_t off = std::min<int64_t>(
@@ -658,24 +709,20 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
         if (hipMemcpy2DAsync(b.A, (size_t)a.n * es, src + (size_t)off * es,
                              (size_t)o->src_n * es, (size_t)a.n * es, 6,
                              hipMemcpyDeviceToDevice, prod) != hipSuccess) {
-          (void)syev3_server_release(s, id);
           rc = SYEV3_E_HIP;
           break;
         }
         batch.push_back(id);
         if ((int)batch.size() == kGroup) flush();
       }
-      admit_wait_sum += seconds_since(t0, Clock::now()) - a.t;
-      admitted++;
-      live[id] = Live{a.t, a.n};
-      waiting.pop_front();
     }
     flush();
     if (rc != SYEV3_OK) break;
     // completions
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      done.swap(s->done_ids);
+      // copy, so that the server's list keeps the capacity reserved for it
+      done.assign(s->done_ids.begin(), s->done_ids.end());
       s->done_ids.clear();
     }
     if (!done.empty()) {
@@ -697,7 +744,12 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
     if (next_t >= o->duration_s && waiting.empty() && live.empty()) break;
     std::this_thread::yield();
   }
-  // drain whatever is still live after an error
+  } catch (const std::bad_alloc&) {
+    rc = SYEV3_E_NOMEM;
+  }
+  // Drain whatever is still live after an error.  Input copies of requests
+  // never submitted may still be running: finish them before any release.
+  (void)hipStreamSynchronize(prod);
   for (auto& kv : live) {
     (void)syev3_server_wait(s, kv.first, 10.0, nullptr);
     (void)syev3_server_release(s, kv.first);

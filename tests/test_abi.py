@@ -37,7 +37,7 @@ def test_library_exports_every_declared_function(L):
 
 
 def test_strerror_and_version(L):
-    for code in range(0, -12, -1):
+    for code in range(0, -13, -1):
         s = L.syev3_strerror(code).decode()
         assert s and s != "unknown error code"
     assert L.syev3_version() >= 10000
@@ -139,3 +139,24 @@ def test_server_rejects_bad_options_without_a_gpu(L):
     assert L.syev3_server_acquire(None, 10, 0, 1, ctypes.byref(b)) == -2
     assert L.syev3_server_submit(None, 0, None) == -10
     assert L.syev3_server_release(None, 0) == -10
+
+
+def test_server_options_are_range_checked(L):
+    """syev3_server_create rejects options outside the documented ranges
+    before it touches the device, and leaves *out NULL."""
+    def opts(**kw):
+        o = _lib.ServerOpts()
+        L.syev3_server_default_opts(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+    bad = [dict(max_requests=0), dict(max_requests=65537), dict(max_requests=-1),
+           dict(max_inflight_ticks=0), dict(max_inflight_ticks=65),
+           dict(max_segments_per_tick=0), dict(max_segments_per_tick=1025),
+           dict(grid_blocks=-1), dict(hbm_budget_bytes=255)]
+    for kw in bad:
+        h = ctypes.c_void_p(0x1234)
+        rc = L.syev3_server_create(ctypes.byref(opts(**kw)), ctypes.byref(h))
+        assert rc == -1, (kw, rc)
+        assert not h.value, kw
+    assert L.syev3_server_create(ctypes.byref(opts()), None) == -2
