@@ -40,9 +40,14 @@
  * on these paths.  Outputs must not overlap the input or each other.
  *
  * Execution: asynchronous on `stream` (a hipStream_t of the current device;
- * NULL is the null stream).  A return of 0 means the work was enqueued.
+ * NULL is the null stream).  A return of 0 means the work was enqueued.  A
+ * batch of more than 2^31 matrices is enqueued as consecutive launches of
+ * at most 2^31 (a dispatch counts its grid in 32 bits); the results are the
+ * same as in one launch.
  *
- * Errors: negative return values, listed below, with nothing enqueued.
+ * Errors: negative return values, listed below, with nothing enqueued
+ * (except SYEV3_E_HIP on a later launch of a split batch, which leaves the
+ * earlier launches enqueued).
  * n == 0 is a no-op returning 0.  Numerical trouble in one matrix never fails
  * a call: a matrix with a NaN or infinite entry gets NaN eigenvalues and
  * eigenvectors.  No C++ exception crosses this interface.  Calls may be made
@@ -154,7 +159,8 @@ int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
  * as batched_syev3 does in SoA layout with ld = n, with trivial arithmetic
  * in between, its workgroups in launch order.  A yardstick for the solver's
  * memory traffic, not a bound: the solver orders its workgroups by XCD for
- * large batches and can run faster.  Same argument rules as batched_syev3.
+ * large batches and can run faster.  Same argument rules as batched_syev3,
+ * and n at most 2^31 (one launch; SYEV3_E_N above).
  */
 int syev3_stream_reference(int64_t n, const void* A_upper6, void* lambda, void* V,
                            int dtype, hipStream_t stream);

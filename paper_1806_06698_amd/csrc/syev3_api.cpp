@@ -108,6 +108,7 @@ int syev3_stream_reference(int64_t n, const void* A, void* lambda, void* V, int 
   int64_t ld = 0;
   const int rc = check_args(n, A, ld, SYEV3_SOA, lambda, V, dtype, 0u);
   if (rc != SYEV3_OK || n == 0) return rc;
+  if (n > ((int64_t)1 << 31)) return SYEV3_E_N;  // one launch
   const hipError_t e = syev3::launch_stream_reference(n, A, lambda, V, dtype, stream);
   return e == hipSuccess ? SYEV3_OK : SYEV3_E_HIP;
 }

@@ -208,16 +208,37 @@ static hipError_t launch_t(int64_t n, const void* A, int64_t ld, int layout,
   return hipGetLastError();
 }
 
+// A dispatch counts its grid in work-items with 32 bits per dimension, so one
+// launch covers at most 2^31 matrices (2^23 workgroups); larger batches are
+// solved by consecutive launches on the same stream.  Each matrix is solved
+// by its own lane, so the split changes no result.
+constexpr int64_t kMaxPerLaunch = (int64_t)1 << 31;
+
 template <typename T>
 static hipError_t launch_dt(int64_t n, const void* A, int64_t ld, int layout,
                             void* lambda, void* V, uint32_t flags, int32_t* info,
                             hipStream_t stream) {
-  if (V) {
-    return info ? launch_t<T, true, true>(n, A, ld, layout, lambda, V, flags, info, stream)
-                : launch_t<T, true, false>(n, A, ld, layout, lambda, V, flags, info, stream);
+  // elements per matrix between consecutive matrices: SoA planes are
+  // offset as a whole (ld is unchanged), AoS rows are packed
+  const int64_t w_in = layout == 0 ? 1 : (layout == 1 ? 6 : 9);
+  const int64_t w_lam = layout == 0 ? 1 : 3, w_v = layout == 0 ? 1 : 9;
+  for (int64_t s = 0; s < n; s += kMaxPerLaunch) {
+    const int64_t m = n - s < kMaxPerLaunch ? n - s : kMaxPerLaunch;
+    const T* As = (const T*)A + s * w_in;
+    T* ls = (T*)lambda + s * w_lam;
+    T* Vs = V ? (T*)V + s * w_v : nullptr;
+    int32_t* is = info ? info + s : nullptr;
+    hipError_t e;
+    if (V) {
+      e = info ? launch_t<T, true, true>(m, As, ld, layout, ls, Vs, flags, is, stream)
+               : launch_t<T, true, false>(m, As, ld, layout, ls, Vs, flags, is, stream);
+    } else {
+      e = info ? launch_t<T, false, true>(m, As, ld, layout, ls, Vs, flags, is, stream)
+               : launch_t<T, false, false>(m, As, ld, layout, ls, Vs, flags, is, stream);
+    }
+    if (e != hipSuccess) return e;
   }
-  return info ? launch_t<T, false, true>(n, A, ld, layout, lambda, V, flags, info, stream)
-              : launch_t<T, false, false>(n, A, ld, layout, lambda, V, flags, info, stream);
+  return hipSuccess;
 }
 
 hipError_t launch_batched(int64_t n, const void* A, int64_t ld, int layout,
@@ -304,21 +325,23 @@ __global__ __launch_bounds__(kBlock) void k_stream_reference(int64_t n, const T*
   }
 }
 
+template <typename T>
+static hipError_t launch_stream_reference_t(int64_t n, const T* A, T* lambda, T* V,
+                                            hipStream_t stream) {
+  const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+  if (V) hipLaunchKernelGGL((k_stream_reference<T, true>), grid, block, 0, stream, n, A, lambda, V);
+  else hipLaunchKernelGGL((k_stream_reference<T, false>), grid, block, 0, stream, n, A, lambda, V);
+  return hipGetLastError();
+}
+
 hipError_t launch_stream_reference(int64_t n, const void* A, void* lambda, void* V,
                                    int dtype, hipStream_t stream) {
-  const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
-  if (dtype == 0) {
-    if (V) hipLaunchKernelGGL((k_stream_reference<double, true>), grid, block, 0, stream, n,
-                              (const double*)A, (double*)lambda, (double*)V);
-    else hipLaunchKernelGGL((k_stream_reference<double, false>), grid, block, 0, stream, n,
-                            (const double*)A, (double*)lambda, (double*)V);
-  } else {
-    if (V) hipLaunchKernelGGL((k_stream_reference<float, true>), grid, block, 0, stream, n,
-                              (const float*)A, (float*)lambda, (float*)V);
-    else hipLaunchKernelGGL((k_stream_reference<float, false>), grid, block, 0, stream, n,
-                            (const float*)A, (float*)lambda, (float*)V);
-  }
-  return hipGetLastError();
+  // the kernel's planes are n apart, so a split batch is not expressible:
+  // the reference is for batches one launch can hold
+  if (n > kMaxPerLaunch) return hipErrorInvalidValue;
+  if (dtype == 0)
+    return launch_stream_reference_t(n, (const double*)A, (double*)lambda, (double*)V, stream);
+  return launch_stream_reference_t(n, (const float*)A, (float*)lambda, (float*)V, stream);
 }
 
 int device_cu_count() {

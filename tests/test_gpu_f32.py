@@ -117,3 +117,39 @@ def test_refinement_is_the_only_difference_on_exact_cases():
     l2, V2 = solve_soa(Ad, refine=False)
     assert Ad.shape[1] > 1000
     assert torch.equal(l1, l2) and torch.equal(V1, V2)
+
+
+def test_batch_split_over_launches():
+    """A batch of more than 2^31 matrices is solved by consecutive launches
+    (a dispatch counts its grid in work-items with 32 bits).  FP32 storage,
+    eigenvalues only, N(0,1) entries, n = 2^31 + 777 (two launches), SoA and
+    then AoS (about 77 GB each): the eigenvalues at both ends and on both
+    sides of the split equal, bitwise, those of one small launch on the same
+    matrices, and those around the split meet the bar against the oracle."""
+    if torch.cuda.get_device_properties(0).total_memory < (160 << 30):
+        pytest.skip("needs about 80 GB of device memory")
+    split = 1 << 31
+    n = split + 777
+    win = torch.from_numpy(np.r_[0:300, split - 300:n]).cuda()
+    for layout in ("soa", "aos"):
+        print(f"split batch: {layout}, n={n}", flush=True)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(51)
+        A = torch.randn((6, n) if layout == "soa" else (n, 6), generator=g,
+                        dtype=torch.float32, device="cuda")
+        lam, _ = s3.syev3(A, layout=layout, vectors=False)
+        Aw = (A[:, win] if layout == "soa" else A[win]).contiguous()
+        got = lam[:, win] if layout == "soa" else lam[win].t()
+        del A, lam
+        lw, _ = s3.syev3(Aw, layout=layout, vectors=False)
+        lw = lw if layout == "soa" else lw.t()
+        torch.cuda.synchronize()
+        assert torch.equal(got, lw)
+        A6 = (Aw.t() if layout == "soa" else Aw).double().cpu().numpy()[300:]
+        lam_o, _ = oracle.solve(A6)
+        e = checks.eig_error(A6, got.t().double().cpu().numpy()[300:], lam_o) * (EPS64 / EPS32)
+        print(f"  {len(A6)} matrices around the split vs oracle: max {e.max():.3f} eps32|A|",
+              flush=True)
+        assert e.max() <= BAR_REFINE["lam"]
+        del Aw, got, lw
+        torch.cuda.empty_cache()
