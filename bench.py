@@ -75,8 +75,10 @@ def copy_calibration(torch):
 
 def timed_launches(fn, steps, warmup, torch):
     """Run fn() warmup times, then steps times with a HIP event pair around
-    each launch on the launching (current) stream.  Returns (total_s,
-    per-launch ms list)."""
+    each launch on the launching (current) stream, with a device
+    synchronisation before and after the timed launches.  Returns (host
+    seconds over the timed launches, per-launch ms list, device seconds from
+    the first launch's start event to the last one's end event)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()

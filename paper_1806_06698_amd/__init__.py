@@ -30,9 +30,13 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def _stream_handle(stream):
+def _stream_handle(stream, device):
+    """The stream to launch on: the given one, else the current stream of the
+    device that holds the data (the launch runs on the stream's device)."""
     if stream is None:
-        stream = torch.cuda.current_stream()
+        stream = torch.cuda.current_stream(device)
+    elif stream.device != device:
+        raise ValueError(f"stream is on {stream.device}, the tensors on {device}")
     return ctypes.c_void_p(stream.cuda_stream)
 
 
@@ -139,7 +143,7 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
     inf = torch.empty(n, dtype=torch.int32, device=A.device) if info else None
     rc = _lib.lib().batched_syev3_info(
         n, _ptr(A), ld, lay, _ptr(lam), _ptr(V), dt, flags, _ptr(inf),
-        _stream_handle(stream))
+        _stream_handle(stream, A.device))
     _lib.check(rc, "batched_syev3_info")
     if info:
         return lam, V, inf
@@ -155,6 +159,6 @@ def syev3_inplace(A: torch.Tensor, *, stream=None) -> torch.Tensor:
         raise ValueError("A must be a contiguous (n, 3, 3) tensor")
     lam = torch.empty((A.shape[0], 3), dtype=A.dtype, device=A.device)
     rc = _lib.lib().batched_syev3_inplace(A.shape[0], _ptr(A), _ptr(lam), _dtype_code(A),
-                                          _stream_handle(stream))
+                                          _stream_handle(stream, A.device))
     _lib.check(rc, "batched_syev3_inplace")
     return lam

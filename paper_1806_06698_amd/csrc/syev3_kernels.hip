@@ -119,6 +119,50 @@ __device__ __forceinline__ void copy_in(T* sm, const T* g, int total, int t) {
   for (int k = k0 + t; k < total; k += kBlock) sm[k] = ld_stream(g + k);
 }
 
+// The same for a full tile, whose size is known at compile time: every lane
+// issues all of its loads (or LDS reads) before the first write, so its
+// memory requests are in flight together rather than one after another.
+// g must be 16-byte aligned.  TOTAL = elements, a multiple of 16 / sizeof(T).
+template <typename T, int TOTAL>
+__device__ __forceinline__ void copy_in_full(T* sm, const T* g, int t) {
+  constexpr int W = 16 / sizeof(T);
+  constexpr int NV = TOTAL / W;
+  constexpr int R = (NV + kBlock - 1) / kBlock;
+  static_assert(TOTAL % W == 0, "whole 16-byte vectors");
+  typedef T vec __attribute__((ext_vector_type(W)));
+  vec x[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int k = t + j * kBlock;
+    if (j + 1 < R || k < NV) x[j] = ld_stream((const vec*)g + k);
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int k = t + j * kBlock;
+    if (j + 1 < R || k < NV) ((vec*)sm)[k] = x[j];
+  }
+}
+
+template <typename T, int TOTAL>
+__device__ __forceinline__ void copy_out_full(T* g, const T* sm, int t) {
+  constexpr int W = 16 / sizeof(T);
+  constexpr int NV = TOTAL / W;
+  constexpr int R = (NV + kBlock - 1) / kBlock;
+  static_assert(TOTAL % W == 0, "whole 16-byte vectors");
+  typedef T vec __attribute__((ext_vector_type(W)));
+  vec x[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int k = t + j * kBlock;
+    if (j + 1 < R || k < NV) x[j] = ((const vec*)sm)[k];
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int k = t + j * kBlock;
+    if (j + 1 < R || k < NV) st_stream(x[j], (vec*)g + k);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void copy_out(T* g, const T* sm, int total, int t) {
   constexpr int W = 16 / sizeof(T);
@@ -148,7 +192,12 @@ __global__ __launch_bounds__(kBlock) void k_syev3_aos(
   const int cnt = (int)((n - base) < kBlock ? (n - base) : kBlock);
   const int t = threadIdx.x;
   const T* Ab = A + base * IN;
-  copy_in(sm, Ab, cnt * IN, t);
+  // full tiles of a 16-byte-aligned array take the unrolled copies (every
+  // tile but the last, when the caller's arrays are aligned)
+  const bool full = cnt == kBlock && ((uintptr_t)A & 15u) == 0 &&
+                    ((uintptr_t)lam & 15u) == 0 && (!VECS || ((uintptr_t)V & 15u) == 0);
+  if (full) copy_in_full<T, kBlock * IN>(sm, Ab, t);
+  else copy_in(sm, Ab, cnt * IN, t);
   __syncthreads();
   double a[6];
   if (t < cnt) {
@@ -170,7 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_syev3_aos(
     if (INFO) info[base + t] = code;
   }
   __syncthreads();
-  copy_out(lam + base * 3, sm, cnt * 3, t);
+  if (full) copy_out_full<T, kBlock * 3>(lam + base * 3, sm, t);
+  else copy_out(lam + base * 3, sm, cnt * 3, t);
   if (VECS) {
     __syncthreads();  // every lambda read from LDS before V overwrites it
     if (t < cnt) {
@@ -178,7 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_syev3_aos(
       for (int k = 0; k < 9; ++k) sm[9 * t + k] = (T)v[k];
     }
     __syncthreads();
-    copy_out(V + base * 9, sm, cnt * 9, t);
+    if (full) copy_out_full<T, kBlock * 9>(V + base * 9, sm, t);
+    else copy_out(V + base * 9, sm, cnt * 9, t);
   }
 }
 
