@@ -92,11 +92,17 @@ __global__ __launch_bounds__(kBlock) void k_syev3_soa32(uint32_t n, Planes<T> P,
     a[k] = (double)ld_stream((const T*)((const char*)P.a[k] + off));
   double l[3], v[9];
   const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v);
+  // The offset is re-defined here (an empty asm emits nothing) so that the
+  // stores, past the solve's branches, again see a 32-bit offset and take
+  // the scalar-base form rather than a 64-bit address add per store: 12
+  // fewer VALU per wavefront, 2.4% faster for the VALU-bound FP32 form.
+  uint32_t soff = off;
+  asm volatile("" : "+v"(soff));
 #pragma unroll
-  for (int j = 0; j < 3; ++j) st_stream((T)l[j], (T*)((char*)P.l[j] + off));
+  for (int j = 0; j < 3; ++j) st_stream((T)l[j], (T*)((char*)P.l[j] + soff));
   if (VECS) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) st_stream((T)v[k], (T*)((char*)P.v[k] + off));
+    for (int k = 0; k < 9; ++k) st_stream((T)v[k], (T*)((char*)P.v[k] + soff));
   }
   if (INFO) info[i] = code;
 }
