@@ -34,6 +34,7 @@ BYTES_PER_MATRIX = {  # algorithmic: 6 entries in, 3 (+9) out
 KERNEL_SOURCES = ["paper_1806_06698_amd/csrc/syev3_lane.hpp",
                   "paper_1806_06698_amd/csrc/syev3_kernels.hip"]
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, published
 
 
 def kernel_hash() -> str:
@@ -95,9 +96,10 @@ def timed_launches(fn, steps, warmup, torch):
     return total, per, starts[0].elapsed_time(ends[-1]) / 1e3
 
 
-def pmc_traffic(n, khash):
-    """HBM bytes per launch from committed rocprofv3 counter runs, or None
-    when they were taken on other kernel sources or another batch size."""
+def pmc_record(n, khash):
+    """The committed rocprofv3 counter figures for the headline kernel, or
+    None when they were taken on other kernel sources or another batch
+    size."""
     try:
         with open(PMC_FILE) as fh:
             d = json.load(fh)
@@ -106,7 +108,29 @@ def pmc_traffic(n, khash):
     ent = d.get("spd_fe_64m_f64_soa")
     if not ent or ent.get("kernel_hash") != khash or ent.get("n") != n:
         return None
-    return ent.get("hbm_bytes_per_launch")
+    return ent
+
+
+def pmc_traffic(n, khash):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated), or None."""
+    ent = pmc_record(n, khash)
+    return ent.get("hbm_bytes_per_launch") if ent else None
+
+
+def fp64_valu_rate(n, khash, ms_launch):
+    """FP64 VALU rate of the headline kernel against the vector FP64 peak:
+    the FP64 VALU instructions of one launch from the committed counters,
+    times 64 lanes (an FMA counts 2 flops; lanes masked off in divergent
+    wavefronts are counted too, so this is an upper bound), divided by the
+    live mean launch time.  None when the counters are stale."""
+    ent = pmc_record(n, khash)
+    if not ent or "fp64_lane_flops_per_launch" not in ent:
+        return None
+    flops = ent["fp64_lane_flops_per_launch"]
+    achieved = flops / (ms_launch * 1e-3) / 1e12
+    return {"achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "lane_flops_per_launch": flops,
+            "valu_instructions_per_launch": ent.get("valu_instructions_per_launch")}
 
 
 def host_info():
@@ -282,6 +306,7 @@ def main():
                      "ms_per_launch_median": sorted(per_ms)[len(per_ms) // 2],
                      "stream_reference_GBps": bytes_launch / (ms_ref * 1e-3) / 1e9,
                      "ratio_to_stream_reference": ms_ref / ms_launch},
+        "fp64_valu": fp64_valu_rate(n, khash, ms_launch),
         "kernel_hash": khash,
     }
     line["zero_finder"] = zero_finder_stats(torch, s3, A)
