@@ -183,3 +183,56 @@ def test_host_staged_loadgen(source):
                           max_log2_n=16, seed=9, sink=sink)
     print(res, flush=True)
     assert res["requests"] > 10 and res["lat_p99_s"] > 0
+
+
+def test_concurrent_clients(source):
+    """Four host threads use one server at once, each on its own stream:
+    acquire (retrying while the small pool is full), fill, submit, wait,
+    check, release.  Every result equals a separate batched solve of the
+    same input bitwise, and the pool ends empty."""
+    import threading
+    import time
+    A64, A32 = source
+    per_thread, errors = 25, []
+
+    def client(k, srv):
+        try:
+            rng = np.random.default_rng(100 + k)
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                for it in range(per_thread):
+                    n = int(rng.integers(1, 20_000))
+                    dt = s3.F64 if (it + k) % 2 == 0 else s3.F32_REFINE
+                    vec = (it + k) % 3 != 0
+                    deadline = time.monotonic() + 30.0
+                    r = srv.acquire(n, dt, vectors=vec)
+                    while r is None:
+                        assert time.monotonic() < deadline, "admission starved"
+                        time.sleep(0.0005)
+                        r = srv.acquire(n, dt, vectors=vec)
+                    off = int(rng.integers(0, (1 << 21) - n))
+                    srv.submit(r, _fill(r, A32 if dt == s3.F32_REFINE else A64, off))
+                    srv.wait(r, timeout_s=30.0)
+                    lam, V = _reference(r)
+                    stream.synchronize()
+                    assert torch.equal(lam, r.lam), f"thread {k}: lambda differs, n={n}"
+                    if vec:
+                        assert torch.equal(V, r.V), f"thread {k}: V differs, n={n}"
+                    srv.release(r)
+        except Exception as exc:  # reported by the main thread
+            errors.append(exc)
+
+    # 6 MB: room for two of the largest FP64 requests with vectors at once
+    with serve.Server(hbm_budget_bytes=6 << 20, max_requests=8) as srv:
+        threads = [threading.Thread(target=client, args=(k, srv)) for k in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(timeout=90.0)
+        assert not any(t.is_alive() for t in threads), "a client did not finish"
+        assert not errors, errors[0]
+        st = srv.stats()
+        assert st["completed"] == 4 * per_thread
+        assert st["pool_bytes_in_use"] == 0 and st["queue_depth"] == 0
+        print(f"concurrent clients: {st['completed']} requests, {st['ticks']} ticks, "
+              f"{st['acquire_rejections']} rejected acquisitions", flush=True)
