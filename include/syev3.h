@@ -99,7 +99,17 @@ extern "C" {
                                      For measuring what the default start
                                      and stop test save; SYEV3_F64 only, not
                                      with SYEV3_FLAG_NEWTON */
-#define SYEV3_FLAGS_ALL 15u
+#define SYEV3_FLAG_REFINE_CONVERGE 16u /* FP32 storage: after the FP64 Newton
+                                     step, continue every root with FP64
+                                     Borges-Gragg steps (Sec. 1.4.1) until
+                                     their stop test, as is otherwise done
+                                     only when the Newton correction exceeds
+                                     2^-12 of the root.  Eigenvalues as
+                                     accurate as the FP64 zero finder makes
+                                     them, for one or two more FP64
+                                     evaluations per root; SYEV3_F32_REFINE
+                                     only */
+#define SYEV3_FLAGS_ALL 31u
 
 /* error codes */
 #define SYEV3_OK 0
@@ -253,7 +263,9 @@ int64_t syev3_server_acquire(syev3_server* s, int64_t n, int dtype,
 
 /* Queue an admitted request for the next tick.  Its A must be complete
  * when `ready` (a hipEvent_t, or NULL) has completed: the tick waits for it
- * on the device, the host does not block. */
+ * on the device, the host does not block.  The wait is enqueued when the
+ * tick is launched, not here, so `ready` must stay valid (not destroyed)
+ * and must not be recorded again until the request is reported done. */
 int syev3_server_submit(syev3_server* s, int64_t request, hipEvent_t ready);
 
 /* Host-staged submission: the request's input is copied from host memory

@@ -17,11 +17,13 @@ import torch
 
 from . import _lib
 from ._lib import (AOS, AOS9, F32, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD,
-                   FLAG_PAPER_BG, FLAG_SIMPLIFIED_DEFLATION, SOA, Syev3Error)
+                   FLAG_PAPER_BG, FLAG_REFINE_CONVERGE, FLAG_SIMPLIFIED_DEFLATION, SOA,
+                   Syev3Error)
 
 __all__ = ["syev3", "syev3_inplace", "batched_syev3", "batched_syev3_ex", "batched_syev3_info",
            "F64", "F32_REFINE", "F32", "SOA", "AOS", "AOS9", "FLAG_SIMPLIFIED_DEFLATION",
-           "FLAG_NO_H_GUARD", "FLAG_NEWTON", "FLAG_PAPER_BG", "Syev3Error", "lib_path"]
+           "FLAG_NO_H_GUARD", "FLAG_NEWTON", "FLAG_PAPER_BG", "FLAG_REFINE_CONVERGE", "Syev3Error",
+           "lib_path"]
 
 lib_path = _lib.LIB_PATH
 

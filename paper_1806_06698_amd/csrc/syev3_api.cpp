@@ -36,6 +36,7 @@ int check_args(int64_t n, const void* A, int64_t& ld, int layout,
   if ((flags & (SYEV3_FLAG_NEWTON | SYEV3_FLAG_PAPER_BG)) && dtype != SYEV3_F64)
     return SYEV3_E_DTYPE;
   if ((flags & SYEV3_FLAG_NEWTON) && (flags & SYEV3_FLAG_PAPER_BG)) return SYEV3_E_FLAGS;
+  if ((flags & SYEV3_FLAG_REFINE_CONVERGE) && dtype != SYEV3_F32_REFINE) return SYEV3_E_DTYPE;
   if (layout != SYEV3_SOA && layout != SYEV3_AOS && layout != SYEV3_AOS9)
     return SYEV3_E_LAYOUT;
   if (n < 0) return SYEV3_E_N;

@@ -48,6 +48,7 @@ constexpr uint32_t kFlagSimplified = 1u;
 constexpr uint32_t kFlagNoHGuard = 2u;
 constexpr uint32_t kFlagNewton = 4u;
 constexpr uint32_t kFlagPaperBG = 8u;
+constexpr uint32_t kFlagRefineConverge = 16u;
 // internal: FP32 zero finder without the FP64 Newton step and without the
 // re-orthogonalisation (an ablation of the refinement); never set by callers
 constexpr uint32_t kFlagUnrefined = 1u << 31;
@@ -647,6 +648,7 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
         } else {
           mu = newton_refine(P1, (double)y1, bad1);
           nu = newton_refine(P2, (double)y2, bad2);
+          if (flags & kFlagRefineConverge) bad1 = bad2 = true;
         }
       }
       if (fb) {
@@ -657,9 +659,10 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
         it2 += j2;
       } else if (bad1 || bad2) {
         // The FP32 zero was too far off for one Newton step (rare: a zero
-        // the FP32 arithmetic does not resolve): continue with FP64
-        // Borges-Gragg steps.  f is concave, so the Newton iterate lies left
-        // of the zero; when it is not positive the FP32 zero was right of it.
+        // the FP32 arithmetic does not resolve), or every root converges
+        // (kFlagRefineConverge): continue with FP64 Borges-Gragg steps.  f
+        // is concave, so the Newton iterate lies left of the zero; when it
+        // is not positive the FP32 zero was right of it.
         if (bad1 && !(mu > 0.0)) mu = (double)y1;
         if (bad2 && !(nu > 0.0)) nu = (double)y2;
         bool s1 = !bad1, s2 = !bad2;

@@ -102,6 +102,7 @@ class Request:
         self.A = _tensor_at(bufs.A, (6, bufs.n), tdt, es)
         self.lam = _tensor_at(bufs.lam, (3, bufs.n), tdt, es)
         self.V = _tensor_at(bufs.V, (9, bufs.n), tdt, es) if bufs.V else None
+        self.ready_event = None  # held from submit to release
 
 
 def _tensor_at(ptr, shape, dtype, esize):
@@ -156,8 +157,13 @@ class Server:
         return Request(self, rid, b, dtype)
 
     def submit(self, req: Request, ready_event=None):
+        """Queue req; its tick waits on the device for ready_event (a
+        torch.cuda.Event recorded after req.A was written).  The server waits
+        on the event only when it launches the tick, so the request keeps a
+        reference to it until release: the caller may drop its own."""
         ev = ctypes.c_void_p(ready_event.cuda_event if ready_event is not None else 0)
         _lib.check(self.L.syev3_server_submit(self.h, req.id, ev), "syev3_server_submit")
+        req.ready_event = ready_event
 
     def submit_host(self, req: Request, host_A, host_lam, host_V=None):
         """Host-staged submission: host_A (6, n), host_lam (3, n), host_V
@@ -182,6 +188,7 @@ class Server:
 
     def release(self, req):
         _lib.check(self.L.syev3_server_release(self.h, req.id), "syev3_server_release")
+        req.ready_event = None
 
     def stats(self) -> dict:
         s = ServerStats()
