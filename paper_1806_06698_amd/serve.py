@@ -103,6 +103,7 @@ class Request:
         self.lam = _tensor_at(bufs.lam, (3, bufs.n), tdt, es)
         self.V = _tensor_at(bufs.V, (9, bufs.n), tdt, es) if bufs.V else None
         self.ready_event = None  # held from submit to release
+        self.host_buffers = None  # likewise, for host-staged requests
 
 
 def _tensor_at(ptr, shape, dtype, esize):
@@ -173,6 +174,8 @@ class Server:
         _lib.check(self.L.syev3_server_submit_host(
             self.h, req.id, host_A.data_ptr(), host_lam.data_ptr(),
             host_V.data_ptr() if host_V is not None else None), "syev3_server_submit_host")
+        # the copies run when the tick does: keep the buffers alive till release
+        req.host_buffers = (host_A, host_lam, host_V)
 
     def poll(self, req):
         lat = ctypes.c_double()
@@ -189,6 +192,7 @@ class Server:
     def release(self, req):
         _lib.check(self.L.syev3_server_release(self.h, req.id), "syev3_server_release")
         req.ready_event = None
+        req.host_buffers = None
 
     def stats(self) -> dict:
         s = ServerStats()
