@@ -18,8 +18,7 @@
  *               quadratic, start from +infinity, relative stop test)
  *   Sec. 1.4.2  Newton's method from the left (alternative zero finder)
  *
- * Readings where the paper is silent (each also recorded in the design
- * notes of the repository):
+ * Readings where the paper is silent:
  *   - Input scaling by a power of two so that max|a_ij| lies in [1,2); the
  *     eigenvalues are scaled back at the end.  Exact, reversible.
  *   - The Jacobi rotation is the textbook symmetric Schur rotation (Golub &
