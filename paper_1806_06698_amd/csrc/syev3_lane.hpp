@@ -359,17 +359,52 @@ __device__ __forceinline__ double bg_step(const Arrow1& P, double x, bool& stop)
 // stop test above save (flag kFlagPaperBG): the start is x_inf, the first
 // iterate from +infinity (Sec. 1.4.1); before each step the iteration stops
 // when f/f' < 2 eps x (the paper's test with C = 2), when rounding has
-// reached the zero (f <= 0), or when the step no longer decreases x.  Each
-// step is bg_step's from the right; its own stop bound is not used.
+// reached the zero (f <= 0), or when the step no longer decreases x.
+// Taking f <= 0 as convergence, it needs a start and steps that do not land
+// left of the zero by more than rounding, so its arithmetic is rounded to
+// about one ulp (ddiv, sqrt2) in the order of the formulas of Sec. 1.4.1.
+// The default finder's 2^-46 primitives would not do here (a start 2^-46
+// left of the zero would be returned as it is); they do there, since that
+// finder iterates from either side and bounds the new iterate.
+// quad_zero_ulp: the positive zero of x^2 - c x - k, k > 0.
+__device__ __forceinline__ double quad_zero_ulp(double c, double k) {
+  const double c2 = 0.5 * c;
+  const double s = dabs(c2) + sqrt2(__builtin_fma(c2, c2, k));
+  return c >= 0.0 ? s : ddiv(k, s);
+}
+// One evaluation of the paper's iteration at x: stop (returning x) when f
+// <= 0 or f/f' < 2 eps x, else the next iterate; a step that does not
+// decrease x stops with x.
 __device__ __forceinline__ double paper_step(const Arrow1& P, double x, bool& stop) {
-  const Spec s = spec_eval(P, x);
-  if (!(s.f > 0.0) || s.f < 2.0 * kEps64 * x * s.fp) {
+  const double p = x + P.ab;
+  const double q1 = ddiv(P.b1s, x), q2 = ddiv(P.b2s, p);
+  const double f = ((x - P.gb) - q1) - q2;
+  const double fp = (1.0 + ddiv(q1, x)) + ddiv(q2, p);
+  if (!(f > 0.0) || ddiv(f, fp) < 2.0 * kEps64 * x) {
     stop = true;
     return x;
   }
-  bool unused = false;
-  const double xn = bg_update(P, x, s, unused);
-  if (!(xn < x)) stop = true;
+  const double w0 = 1.0 + ddiv(ddiv(q2, p) * P.ab, p);
+  const double a = -ddiv(w0, x);
+  const double b = fp + ddiv(f, x);
+  const double F = ddiv(2.0 * f, b);
+  const double D = __builtin_fmax(0.0, 1.0 + ddiv(2.0 * a, b) * F);
+  const double dl = ddiv(F, 1.0 + sqrt2(D));
+  double xn;
+  if (dl <= 0.5 * x) {
+    xn = x - dl;
+  } else {
+    // the zero of the model itself (see bg_update)
+    const double r = ddiv(x, p);
+    const double w1 = P.b1s + P.b2s * r * r * r;
+    const double sigma = (w0 * x - ddiv(w1, x)) - f;
+    const double sq = sqrt2(sigma * sigma + 4.0 * w0 * w1);
+    xn = sigma >= 0.0 ? ddiv(sigma + sq, 2.0 * w0) : ddiv(2.0 * w1, sq - sigma);
+  }
+  if (!(xn < x)) {
+    stop = true;
+    return x;
+  }
   return xn;
 }
 
@@ -414,8 +449,8 @@ __device__ __forceinline__ void zeros_bg(const Arrow1& P1, const Arrow1& P2,
 
 __device__ __forceinline__ void zeros_bg_paper(const Arrow1& P1, const Arrow1& P2,
                                                double& x1, double& x2, int& it1, int& it2) {
-  x1 = quad_zero(P1.gb, P1.b1s + P1.b2s, 1.0);
-  x2 = quad_zero(P2.gb, P2.b1s + P2.b2s, 1.0);
+  x1 = quad_zero_ulp(P1.gb, P1.b1s + P1.b2s);
+  x2 = quad_zero_ulp(P2.gb, P2.b1s + P2.b2s);
   bool s1 = false, s2 = false;
   it1 = 0;
   it2 = 0;

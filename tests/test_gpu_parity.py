@@ -91,10 +91,10 @@ def test_paper_zero_finder_takes_the_oracles_steps():
     the oracle does: the number of evaluations per root matches the
     oracle's on at least 95% of the roots and has the same mean to two
     digits, meets the bar on the stress mix, and averages several times the
-    default zero finder's count.  (The two evaluate f with different
-    division sequences and test f < 2 eps x f' against f/f' < 2 eps x, so a
-    stop within rounding of the threshold can fall one evaluation apart;
-    97.6% agree on this input.)"""
+    default zero finder's count.  (Both round each division and square
+    root to about one ulp, the oracle exactly, so a stop within rounding of
+    the threshold can fall one evaluation apart; 97.9% agree on this
+    input.)"""
     A, _ = gen.stress_mix(100_000, 33, "cpu")
     lam, V = _compare_full(A, flags=s3.FLAG_PAPER_BG, oflags=0, label="paper BG/stress")
     _, _, info = solve_soa(A.cuda(), flags=s3.FLAG_PAPER_BG, info=True)
