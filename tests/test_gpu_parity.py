@@ -97,6 +97,13 @@ def test_paper_zero_finder_takes_the_oracles_steps():
     input.)"""
     A, _ = gen.stress_mix(100_000, 33, "cpu")
     lam, V = _compare_full(A, flags=s3.FLAG_PAPER_BG, oflags=0, label="paper BG/stress")
+    # the same algorithm as the oracle, rounded alike: its eigenvalues stay
+    # within a few eps of the oracle's (steps rounded to 2^-46 had put them
+    # 9 eps away here)
+    A6 = gen.to_aos(A).numpy()
+    lam_o, _ = oracle.solve(A6)
+    e = checks.eig_error(A6, lam, lam_o)
+    assert e.max() <= 6.0, e.max()
     _, _, info = solve_soa(A.cuda(), flags=s3.FLAG_PAPER_BG, info=True)
     _, _, info_d = solve_soa(A.cuda(), info=True)
     info, info_d = info.cpu().numpy(), info_d.cpu().numpy()
