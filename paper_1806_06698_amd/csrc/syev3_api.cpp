@@ -81,6 +81,11 @@ int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
         overlap(ri, span(V, n, ld, layout, 9, es)))
       return SYEV3_E_ALIAS;
   }
+  // The launchers read the launch status with hipGetLastError, which also
+  // returns an error left by any earlier HIP call of this thread (a failed
+  // allocation the caller recovered from, say): clear it first, so that the
+  // status is this launch's own.
+  (void)hipGetLastError();
   const hipError_t e = syev3::launch_batched(n, A, ld, layout, lambda, V, dtype,
                                              flags, info, stream);
   return e == hipSuccess ? SYEV3_OK : SYEV3_E_HIP;
@@ -110,6 +115,7 @@ int syev3_stream_reference(int64_t n, const void* A, void* lambda, void* V, int 
   const int rc = check_args(n, A, ld, SYEV3_SOA, lambda, V, dtype, 0u);
   if (rc != SYEV3_OK || n == 0) return rc;
   if (n > ((int64_t)1 << 31)) return SYEV3_E_N;  // one launch
+  (void)hipGetLastError();  // a stale error is not this launch's
   const hipError_t e = syev3::launch_stream_reference(n, A, lambda, V, dtype, stream);
   return e == hipSuccess ? SYEV3_OK : SYEV3_E_HIP;
 }

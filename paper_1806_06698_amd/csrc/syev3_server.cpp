@@ -194,6 +194,8 @@ int syev3_server::launch_tick(int slot) {
       e = hipGraphLaunch(tk.exec, tk.stream);
     } else {
       e = hipMemcpyAsync(tk.d_table, tk.h_table, table_bytes, hipMemcpyHostToDevice, tk.stream);
+      // launch_segments reads hipGetLastError: clear any stale error first
+      if (e == hipSuccess) (void)hipGetLastError();
       if (e == hipSuccess) e = syev3::launch_segments(tk.d_table, grid_blocks, tk.stream);
     }
   }
@@ -324,6 +326,7 @@ int syev3_server::init(const syev3_server_opts& opts) {
       if (ok) {
         ok = hipMemcpyAsync(tk.d_table, tk.h_table, table_bytes, hipMemcpyHostToDevice,
                             tk.stream) == hipSuccess;
+        (void)hipGetLastError();  // launch_segments reads it: drop any stale error
         ok = ok && syev3::launch_segments(tk.d_table, grid_blocks, tk.stream) == hipSuccess;
         const bool ended = hipStreamEndCapture(tk.stream, &tk.graph) == hipSuccess;
         ok = ok && ended;

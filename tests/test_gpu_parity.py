@@ -453,3 +453,22 @@ def test_aos_arrays_not_16_byte_aligned(dtype, layout):
     assert rc == 0
     assert torch.equal(lbuf[1:].view(n, 3), lam_ref)
     assert torch.equal(vbuf[1:].view(n, 3, 3), V_ref)
+
+
+def test_a_stale_hip_error_does_not_fail_a_launch():
+    """An error an earlier HIP call left behind (here a failed allocation, as
+    a caller recovering from out-of-memory would leave) is not reported as
+    the next solve's launch failure."""
+    import ctypes
+    A = gen.normal(4096, 61, "cuda")
+    lam_ref, V_ref = s3.syev3(A)
+    torch.cuda.synchronize()
+    path = next(l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64.so" in l)
+    hip = ctypes.CDLL(path)  # the instance already loaded in this process
+    p = ctypes.c_void_p()
+    assert hip.hipMalloc(ctypes.byref(p), ctypes.c_size_t(1 << 60)) != 0
+    # no other kernel launch in between (torch's own launch check would
+    # report the stale error as its failure)
+    lam, V = s3.syev3(A)
+    torch.cuda.synchronize()
+    assert torch.equal(lam, lam_ref) and torch.equal(V, V_ref)

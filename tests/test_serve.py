@@ -236,3 +236,23 @@ def test_concurrent_clients(source):
         assert st["pool_bytes_in_use"] == 0 and st["queue_depth"] == 0
         print(f"concurrent clients: {st['completed']} requests, {st['ticks']} ticks, "
               f"{st['acquire_rejections']} rejected acquisitions", flush=True)
+
+
+def test_create_failures_and_limits():
+    """A pool larger than the device fails with SYEV3_E_BUDGET after freeing
+    what creation had made; the largest allowed max_requests works."""
+    total = torch.cuda.get_device_properties(0).total_memory
+    with pytest.raises(s3.Syev3Error) as exc:
+        serve.Server(hbm_budget_bytes=total + (64 << 30))
+    assert exc.value.code == -8
+    with serve.Server(hbm_budget_bytes=64 << 20, max_requests=65536) as srv:
+        r = srv.acquire(1000, s3.F64)
+        A = torch.randn(6, 1000, dtype=torch.float64, device="cuda")
+        r.A.copy_(A)
+        ev = torch.cuda.Event()
+        ev.record()
+        srv.submit(r, ev)
+        srv.wait(r, timeout_s=30.0)
+        _check_bitwise(r)
+        srv.release(r)
+        assert srv.stats()["pool_bytes_in_use"] == 0
