@@ -47,7 +47,9 @@
  *
  * Errors: negative return values, listed below, with nothing enqueued
  * (except SYEV3_E_HIP on a later launch of a split batch, which leaves the
- * earlier launches enqueued).
+ * earlier launches enqueued).  Before it launches, a call clears any error
+ * an earlier HIP call of the thread left pending (hipGetLastError), so that
+ * SYEV3_E_HIP reports this launch only.
  * n == 0 is a no-op returning 0.  Numerical trouble in one matrix never fails
  * a call: a matrix with a NaN or infinite entry gets NaN eigenvalues and
  * eigenvectors.  No C++ exception crosses this interface.  Calls may be made
