@@ -254,7 +254,9 @@ void syev3_server_default_opts(syev3_server_opts* opts);
  * SYEV3_E_HIP for another HIP failure (streams, events, graphs). */
 int syev3_server_create(const syev3_server_opts* opts, syev3_server** out);
 
-/* Stop the scheduler (after in-flight ticks finish) and free everything. */
+/* Stop the scheduler (after the queued and in-flight ticks finish) and free
+ * everything.  No other call on this server may be in progress (a thread
+ * blocked in syev3_server_wait, say) or follow. */
 int syev3_server_destroy(syev3_server* s);
 
 /* Admit a request of n matrices (vals+vecs if want_vectors) of dtype.

@@ -137,9 +137,17 @@ class Server:
         self.h = h
 
     def close(self):
-        if self.h:
+        if getattr(self, "h", None):
             _lib.check(self.L.syev3_server_destroy(self.h), "syev3_server_destroy")
             self.h = None
+
+    def __del__(self):
+        # a server dropped without close(): stop its scheduler thread while
+        # the runtime is still up (best effort; close() is the way)
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def __enter__(self):
         return self
