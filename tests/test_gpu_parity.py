@@ -472,3 +472,29 @@ def test_a_stale_hip_error_does_not_fail_a_launch():
     lam, V = s3.syev3(A)
     torch.cuda.synchronize()
     assert torch.equal(lam, lam_ref) and torch.equal(V, V_ref)
+
+
+def test_explicit_stream_and_fp32_plane_stride():
+    """The binding's stream argument: input written on a side stream and
+    solved on it without a host synchronisation in between gives the same
+    bits as a solve on the default stream; an FP32 SoA input that is a
+    slice of a wider buffer (ld > n) likewise."""
+    A = gen.stress_mix(50_001, 62, "cuda")[0]
+    lam_ref, V_ref = solve_soa(A)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        B = torch.empty_like(A)
+    B.record_stream(side)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.copy_(A)
+    lam, V = s3.syev3(B, stream=side)
+    side.synchronize()
+    assert torch.equal(lam, lam_ref) and torch.equal(V, V_ref)
+    n, ld = 40_003, 40_960
+    W = torch.zeros(6, ld, dtype=torch.float32, device="cuda")
+    W[:, :n] = A[:, :n].float()
+    lam_s, V_s = solve_soa(W[:, :n])
+    lam_c, V_c = solve_soa(W[:, :n].contiguous())
+    assert lam_s.stride(0) == ld
+    assert torch.equal(lam_s, lam_c) and torch.equal(V_s, V_c)
