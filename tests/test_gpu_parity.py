@@ -498,3 +498,25 @@ def test_explicit_stream_and_fp32_plane_stride():
     lam_c, V_c = solve_soa(W[:, :n].contiguous())
     assert lam_s.stride(0) == ld
     assert torch.equal(lam_s, lam_c) and torch.equal(V_s, V_c)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_aos_tile_boundaries(dtype):
+    """AoS and full-matrix AoS around the 256-matrix tile: full tiles take
+    the unrolled LDS copies, the last tile the loops; both equal the SoA
+    solve bitwise."""
+    A, _ = gen.stress_mix(513, 63, "cuda")
+    A = A.to(dtype)
+    for n in (1, 255, 256, 257, 511, 512, 513):
+        As = A[:, :n].contiguous()
+        lam_s, V_s = solve_soa(As)
+        lam_a, V_a = solve_soa(As.t().contiguous(), layout="aos")
+        full = torch.zeros(n, 3, 3, dtype=dtype, device="cuda")
+        iu = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+        for k, (i, j) in enumerate(iu):
+            full[:, i, j] = As[k]
+            full[:, j, i] = As[k]
+        lam_9, V_9 = solve_soa(full, layout="aos9")
+        assert torch.equal(lam_s.t(), lam_a) and torch.equal(lam_s.t(), lam_9), n
+        assert torch.equal(V_s.t().reshape(-1, 3, 3), V_a), n
+        assert torch.equal(V_a, V_9), n

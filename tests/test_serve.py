@@ -256,3 +256,24 @@ def test_create_failures_and_limits():
         _check_bitwise(r)
         srv.release(r)
         assert srv.stats()["pool_bytes_in_use"] == 0
+
+
+def test_one_segment_per_tick(source):
+    """The smallest configuration: one request per tick, one tick in flight.
+    Every request still completes with the bits of a separate solve."""
+    A64, A32 = source
+    with serve.Server(hbm_budget_bytes=256 << 20, max_inflight_ticks=1,
+                      max_segments_per_tick=1) as srv:
+        reqs = []
+        for k in range(12):
+            dt = s3.F64 if k % 2 == 0 else s3.F32_REFINE
+            r = srv.acquire(1000 + 37 * k, dt, vectors=k % 3 != 2)
+            srv.submit(r, _fill(r, A64 if dt == s3.F64 else A32, 1000 * k))
+            reqs.append(r)
+        for r in reqs:
+            srv.wait(r, timeout_s=30.0)
+            _check_bitwise(r)
+            srv.release(r)
+        st = srv.stats()
+        assert st["ticks"] == 12 and st["segments_per_tick_peak"] == 1
+        assert st["inflight_ticks_peak"] == 1
