@@ -281,6 +281,20 @@ def main():
 
     _, ref_ms, _ = timed_launches(stream_ref, max(5, args.steps // 2), 2, torch)
     ms_ref = sum(ref_ms) / len(ref_ms)
+
+    # the same traffic split: loads only and stores only, in the solver's
+    # workgroup order.  Run one after the other they take t_read + t_write,
+    # the practical floor for this mix of reads and writes.
+    def probe_ms(mode):
+        def run():
+            rc = _lib.lib().syev3_stream_probe(n, ctypes.c_void_p(A.data_ptr()),
+                                               ctypes.c_void_p(lam.data_ptr()),
+                                               ctypes.c_void_p(V.data_ptr()), 0, mode, sh)
+            _lib.check(rc, "syev3_stream_probe")
+        _, ms, _ = timed_launches(run, max(5, args.steps // 2), 2, torch)
+        return sum(ms) / len(ms)
+
+    t_read, t_write, t_both = probe_ms(1 | 4), probe_ms(2 | 4), probe_ms(1 | 2 | 4)
     ms_per_step = span_s * 1e3 / args.steps
     value = n * args.steps / span_s
     bytes_launch = BYTES_PER_MATRIX[("f64", True)] * n
@@ -310,7 +324,13 @@ def main():
                      "ms_per_launch": ms_launch,
                      "ms_per_launch_median": sorted(per_ms)[len(per_ms) // 2],
                      "stream_reference_GBps": bytes_launch / (ms_ref * 1e-3) / 1e9,
-                     "ratio_to_stream_reference": ms_ref / ms_launch},
+                     "ratio_to_stream_reference": ms_ref / ms_launch,
+                     "probes_xcd_order": {
+                         "read_only_GBps": 48 * n / (t_read * 1e-3) / 1e9,
+                         "write_only_GBps": 96 * n / (t_write * 1e-3) / 1e9,
+                         "read_write_GBps": bytes_launch / (t_both * 1e-3) / 1e9,
+                         "serial_bound_ms": t_read + t_write,
+                         "serial_bound_over_ms_per_launch": (t_read + t_write) / ms_launch}},
         "fp64_valu": fp64_valu_rate(n, khash, ms_launch),
         "kernel_hash": khash,
     }

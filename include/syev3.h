@@ -177,6 +177,24 @@ int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
 int syev3_stream_reference(int64_t n, const void* A_upper6, void* lambda, void* V,
                            int dtype, hipStream_t stream);
 
+/*
+ * syev3_stream_probe -- measurement aid, not a solver: the loads and/or the
+ * stores of the SoA solve (ld = n) with trivial arithmetic, for measuring
+ * what HBM sustains for each part of this traffic on the device.  mode is
+ * a bitwise OR of SYEV3_PROBE_READ (read the 6 input planes),
+ * SYEV3_PROBE_WRITE (write the 3 + 9 output planes; V may be NULL) and
+ * SYEV3_PROBE_XCD_ORDER (run the workgroups in the solver's XCD-chunked
+ * order; else launch order), with READ or WRITE or both.  A read-only probe
+ * writes nothing for finite input (its one store is taken only for a NaN
+ * sum).  syev3_stream_reference is mode READ | WRITE.  Same argument rules
+ * as syev3_stream_reference; SYEV3_E_FLAGS for another mode.
+ */
+#define SYEV3_PROBE_READ 1u
+#define SYEV3_PROBE_WRITE 2u
+#define SYEV3_PROBE_XCD_ORDER 4u
+int syev3_stream_probe(int64_t n, const void* A_upper6, void* lambda, void* V, int dtype,
+                       uint32_t mode, hipStream_t stream);
+
 /* Text for an error code (static storage). */
 const char* syev3_strerror(int code);
 

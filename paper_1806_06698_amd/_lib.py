@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
     L.batched_syev3_info.restype = i32
     L.syev3_stream_reference.argtypes = [i64, vp, vp, vp, i32, vp]
     L.syev3_stream_reference.restype = i32
+    L.syev3_stream_probe.argtypes = [i64, vp, vp, vp, i32, u32, vp]
+    L.syev3_stream_probe.restype = i32
     L.syev3_strerror.argtypes = [i32]
     L.syev3_strerror.restype = ctypes.c_char_p
     L.syev3_version.argtypes = []

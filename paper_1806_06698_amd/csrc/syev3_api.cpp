@@ -109,15 +109,24 @@ int batched_syev3_inplace(int64_t n, void* A, void* lambda, int dtype,
   return batched_syev3_info(n, A, 0, SYEV3_AOS9, lambda, A, dtype, 0u, nullptr, stream);
 }
 
-int syev3_stream_reference(int64_t n, const void* A, void* lambda, void* V, int dtype,
-                           hipStream_t stream) {
+int syev3_stream_probe(int64_t n, const void* A, void* lambda, void* V, int dtype,
+                       uint32_t mode, hipStream_t stream) {
+  if ((mode & ~(SYEV3_PROBE_READ | SYEV3_PROBE_WRITE | SYEV3_PROBE_XCD_ORDER)) ||
+      !(mode & (SYEV3_PROBE_READ | SYEV3_PROBE_WRITE)))
+    return SYEV3_E_FLAGS;
   int64_t ld = 0;
   const int rc = check_args(n, A, ld, SYEV3_SOA, lambda, V, dtype, 0u);
   if (rc != SYEV3_OK || n == 0) return rc;
   if (n > ((int64_t)1 << 31)) return SYEV3_E_N;  // one launch
   (void)hipGetLastError();  // a stale error is not this launch's
-  const hipError_t e = syev3::launch_stream_reference(n, A, lambda, V, dtype, stream);
+  const hipError_t e = syev3::launch_stream_probe(n, A, lambda, V, dtype, mode, stream);
   return e == hipSuccess ? SYEV3_OK : SYEV3_E_HIP;
+}
+
+int syev3_stream_reference(int64_t n, const void* A, void* lambda, void* V, int dtype,
+                           hipStream_t stream) {
+  return syev3_stream_probe(n, A, lambda, V, dtype, SYEV3_PROBE_READ | SYEV3_PROBE_WRITE,
+                            stream);
 }
 
 const char* syev3_strerror(int code) {

@@ -31,9 +31,10 @@ struct Segment {
   uint32_t flags;
 };
 
-// The solver's SoA memory traffic with trivial arithmetic (measurement aid).
-hipError_t launch_stream_reference(int64_t n, const void* A, void* lambda, void* V,
-                                   int dtype, hipStream_t stream);
+// The solver's SoA loads and/or stores with trivial arithmetic (measurement
+// aid); mode: SYEV3_PROBE_* bits, at least one of READ and WRITE.
+hipError_t launch_stream_probe(int64_t n, const void* A, void* lambda, void* V, int dtype,
+                               uint32_t mode, hipStream_t stream);
 
 // A tick's table in device memory: header, then the segments in ascending
 // tile_begin order.  Sized for kMaxSegmentsPerTick; only nseg are read.

@@ -362,43 +362,72 @@ hipError_t launch_segments(const TickTable* table, int32_t grid_blocks,
 }
 
 // ---------------------------------------------------------------------------
-// Streaming reference: the SoA kernel's loads and stores, with a sum in
-// place of the solve.
+// Streaming probes: the SoA kernel's loads (RD) and/or stores (WR), with a
+// sum in place of the solve, in launch order or in the solver's XCD-chunked
+// workgroup order.  A read-only probe's one store is taken only for a NaN
+// sum, so its loads are kept and it writes nothing for finite input.  RD and
+// WR together in launch order is the streaming reference.
 // ---------------------------------------------------------------------------
-template <typename T, bool VECS>
+template <typename T, bool VECS, bool RD, bool WR, bool XCD>
 __global__ __launch_bounds__(kBlock) void k_stream_reference(int64_t n, const T* __restrict__ A,
                                                              T* __restrict__ lam,
                                                              T* __restrict__ V) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t b = XCD ? tile_of_block(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int64_t i = (int64_t)b * kBlock + threadIdx.x;
   if (i >= n) return;
-  T s = 0;
+  T s = RD ? (T)0 : (T)threadIdx.x;
+  if (RD) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) s += ld_stream(A + k * n + i);
+    for (int k = 0; k < 6; ++k) s += ld_stream(A + k * n + i);
+  }
+  if (WR) {
 #pragma unroll
-  for (int j = 0; j < 3; ++j) st_stream(s * (T)(j + 1), lam + j * n + i);
-  if (VECS) {
+    for (int j = 0; j < 3; ++j) st_stream(s * (T)(j + 1), lam + j * n + i);
+    if (VECS) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) st_stream(s * (T)(k + 4), V + k * n + i);
+      for (int k = 0; k < 9; ++k) st_stream(s * (T)(k + 4), V + k * n + i);
+    }
+  } else if (__builtin_isnan(s)) {
+    lam[i] = s;
   }
 }
 
-template <typename T>
-static hipError_t launch_stream_reference_t(int64_t n, const T* A, T* lambda, T* V,
-                                            hipStream_t stream) {
+template <typename T, bool VECS>
+static hipError_t launch_probe_t(int64_t n, const T* A, T* lambda, T* V, uint32_t mode,
+                                 hipStream_t stream) {
   const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
-  if (V) hipLaunchKernelGGL((k_stream_reference<T, true>), grid, block, 0, stream, n, A, lambda, V);
-  else hipLaunchKernelGGL((k_stream_reference<T, false>), grid, block, 0, stream, n, A, lambda, V);
-  return hipGetLastError();
+  const bool rd = mode & 1u, wr = mode & 2u, xcd = mode & 4u;
+#define SYEV3_PROBE_CASE(R, W, X)                                                         \
+  if (rd == R && wr == W && xcd == X) {                                                   \
+    hipLaunchKernelGGL((k_stream_reference<T, VECS, R, W, X>), grid, block, 0, stream, n, \
+                       A, lambda, V);                                                     \
+    return hipGetLastError();                                                             \
+  }
+  SYEV3_PROBE_CASE(true, true, false)
+  SYEV3_PROBE_CASE(true, true, true)
+  SYEV3_PROBE_CASE(true, false, false)
+  SYEV3_PROBE_CASE(true, false, true)
+  SYEV3_PROBE_CASE(false, true, false)
+  SYEV3_PROBE_CASE(false, true, true)
+#undef SYEV3_PROBE_CASE
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_stream_reference(int64_t n, const void* A, void* lambda, void* V,
-                                   int dtype, hipStream_t stream) {
+hipError_t launch_stream_probe(int64_t n, const void* A, void* lambda, void* V, int dtype,
+                               uint32_t mode, hipStream_t stream) {
   // the kernel's planes are n apart, so a split batch is not expressible:
-  // the reference is for batches one launch can hold
+  // the probes are for batches one launch can hold
   if (n > kMaxPerLaunch) return hipErrorInvalidValue;
-  if (dtype == 0)
-    return launch_stream_reference_t(n, (const double*)A, (double*)lambda, (double*)V, stream);
-  return launch_stream_reference_t(n, (const float*)A, (float*)lambda, (float*)V, stream);
+  if (dtype == 0) {
+    return V ? launch_probe_t<double, true>(n, (const double*)A, (double*)lambda, (double*)V,
+                                            mode, stream)
+             : launch_probe_t<double, false>(n, (const double*)A, (double*)lambda, nullptr,
+                                             mode, stream);
+  }
+  return V ? launch_probe_t<float, true>(n, (const float*)A, (float*)lambda, (float*)V, mode,
+                                         stream)
+           : launch_probe_t<float, false>(n, (const float*)A, (float*)lambda, nullptr, mode,
+                                          stream);
 }
 
 int device_cu_count() {

@@ -36,8 +36,8 @@ hipError_t launch_batched(int64_t n, const void* A, int64_t ld, int layout, void
   g_launch = Launch{g_launch.count + 1, n, ld, layout, dtype, A, lambda, V, flags, info};
   return hipSuccess;
 }
-hipError_t launch_stream_reference(int64_t n, const void* A, void* lambda, void* V, int dtype,
-                                   hipStream_t) {
+hipError_t launch_stream_probe(int64_t n, const void* A, void* lambda, void* V, int dtype,
+                               uint32_t, hipStream_t) {
   g_launch = Launch{g_launch.count + 1, n, n, 0, dtype, A, lambda, V, 0u, nullptr};
   return hipSuccess;
 }

@@ -143,6 +143,17 @@ def test_server_rejects_bad_options_without_a_gpu(L):
     assert L.syev3_server_release(None, 0) == -10
 
 
+def test_stream_probe_modes_are_checked(L, no_device):
+    probe = _rejecting(L.syev3_stream_probe)
+    assert probe(10, A, LAM, VV, 0, 0, S) == -7               # neither read nor write
+    assert probe(10, A, LAM, VV, 0, 4, S) == -7               # order alone
+    assert probe(10, A, LAM, VV, 0, 8, S) == -7               # unknown bit
+    assert probe(10, A, LAM, VV, 5, 3, S) == -3               # dtype
+    assert probe(-1, A, LAM, VV, 0, 3, S) == -1
+    far = [ctypes.c_void_p(x << 40) for x in (1, 2, 3)]        # no overlap at this size
+    assert probe((1 << 31) + 1, *far, 0, 3, S) == -1          # more than one launch
+
+
 def test_server_options_are_range_checked(L):
     """syev3_server_create rejects options outside the documented ranges
     before it touches the device, and leaves *out NULL."""

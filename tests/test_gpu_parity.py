@@ -520,3 +520,27 @@ def test_aos_tile_boundaries(dtype):
         assert torch.equal(lam_s.t(), lam_a) and torch.equal(lam_s.t(), lam_9), n
         assert torch.equal(V_s.t().reshape(-1, 3, 3), V_a), n
         assert torch.equal(V_a, V_9), n
+
+
+def test_stream_probes_touch_what_they_say():
+    """syev3_stream_probe: a read-only probe writes nothing for finite
+    input; a write-only probe writes every output element; the reference
+    (read and write) writes them from the input."""
+    import ctypes
+    from paper_1806_06698_amd import _lib
+    n = 3 * 65536 + 17
+    A = gen.normal(n, 64, "cuda")
+    sh = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L = _lib.lib()
+    for mode in (1, 5, 2, 6, 3, 7):
+        lam = torch.full((3, n), -7.0, dtype=torch.float64, device="cuda")
+        V = torch.full((9, n), -7.0, dtype=torch.float64, device="cuda")
+        rc = L.syev3_stream_probe(n, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                  ctypes.c_void_p(V.data_ptr()), 0, mode, sh)
+        assert rc == 0
+        torch.cuda.synchronize()
+        untouched = bool((lam == -7.0).all() and (V == -7.0).all())
+        if mode & 2:
+            assert not (lam == -7.0).any() and not (V == -7.0).any(), mode
+        else:
+            assert untouched, mode
