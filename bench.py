@@ -345,16 +345,28 @@ def main():
     }
     if ref_error:
         line["roofline"]["stream_reference_error"] = ref_error
-    line["zero_finder"] = zero_finder_stats(torch, s3, A)
+    def guarded(fn, *a, **kw):
+        """A supporting measurement: its failure is reported, not raised."""
+        try:
+            return fn(*a, **kw)
+        except Exception as exc:
+            torch.cuda.empty_cache()
+            return {"error": repr(exc)}
+
+    line["zero_finder"] = guarded(zero_finder_stats, torch, s3, A)
     if not args.headline_only:
-        line["zero_finder_paper_bg"] = zero_finder_stats(torch, s3, A, flags=s3.FLAG_PAPER_BG)
+        line["zero_finder_paper_bg"] = guarded(zero_finder_stats, torch, s3, A,
+                                               flags=s3.FLAG_PAPER_BG)
     del A, lam, V
     torch.cuda.empty_cache()
 
     if not args.headline_only:
         side = {}
 
-        def run_variant(name, A, layout, vectors, dtype_key, steps=10, flags=0):
+        def run_variant(name, *a, **kw):
+            side[name] = guarded(time_variant, *a, **kw)
+
+        def time_variant(A, layout, vectors, dtype_key, steps=10, flags=0):
             nn = A.shape[1] if layout == "soa" else A.shape[0]
             refine = dtype_key != "f32"
             out = s3.syev3(A, layout=layout, vectors=vectors, refine=refine, flags=flags)
@@ -364,10 +376,10 @@ def main():
             _, per, span = timed_launches(fn, steps, 5, torch)  # 5 warm-up launches
             msl = sum(per) / len(per)
             b = BYTES_PER_MATRIX[(dtype_key, vectors)] * nn
-            side[name] = {"n": nn, "ms_per_launch": msl, "eigensolves_per_s": nn / (msl * 1e-3),
-                          "algorithmic_GBps": b / (msl * 1e-3) / 1e9,
-                          "hbm_frac": b / (msl * 1e-3) / 1e9 / HBM_PEAK_GBS}
             del out
+            return {"n": nn, "ms_per_launch": msl, "eigensolves_per_s": nn / (msl * 1e-3),
+                    "algorithmic_GBps": b / (msl * 1e-3) / 1e9,
+                    "hbm_frac": b / (msl * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
         A = gen.spd_fe(n, seed=2, device=dev)
         Af = A.float()
@@ -386,8 +398,9 @@ def main():
         Aa = A.t().contiguous()
         run_variant("spd_fe_64m_f64_aos", Aa, "aos", True, "f64")
         del Aa, Af
-        side["f32r_speedup_vs_f64"] = (line["roofline"]["ms_per_launch"]
-                                       / side["spd_fe_64m_f32r_soa"]["ms_per_launch"])
+        f32r_ms = side["spd_fe_64m_f32r_soa"].get("ms_per_launch")
+        side["f32r_speedup_vs_f64"] = (line["roofline"]["ms_per_launch"] / f32r_ms
+                                       if f32r_ms else None)
         del A
         torch.cuda.empty_cache()
         A, _ = gen.stress_mix(1 << 24, seed=1, device=dev)
