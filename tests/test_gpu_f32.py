@@ -155,6 +155,44 @@ def test_refinement_is_the_only_difference_on_exact_cases():
     assert torch.equal(l1, l2) and torch.equal(V1, V2)
 
 
+@pytest.mark.parametrize("refine,flags", [(True, 0), (False, 0),
+                                          (True, s3.FLAG_REFINE_CONVERGE)])
+def test_scaling_to_the_ends_of_the_float_range(refine, flags):
+    """Integer matrices (|a| <= 4000 < 2^12) scaled by 2^-140, where every
+    nonzero entry is an FP32 subnormal (still exact: a multiple of 2^-149),
+    and by 2^113, where |lambda| <= ||A||_F <= 12000 * 2^113 < 2^127 still
+    fits.  The solver widens to FP64 and takes out the same power of two, so
+    it sees the same matrix: V is bitwise unchanged.  lambda is unscaled in
+    FP64 and rounded to FP32 once, so at 2^113 it is the scaled result
+    exactly; at 2^-140 it lies within one subnormal step (2^-149) of it,
+    and equals it wherever the scaled result is representable (rounding the
+    FP64 value straight to the subnormal grid, or first to 24 bits, then
+    agrees)."""
+    g = np.random.default_rng(53)
+    A6 = g.integers(-4000, 4001, size=(50_000, 6)).astype(np.float64)
+    kw = dict(refine=refine, flags=flags)
+    lam0, V0 = solve_soa(torch.from_numpy(np.ascontiguousarray(A6.T, np.float32)).cuda(), **kw)
+    lam0 = lam0.cpu().numpy().astype(np.float64)
+    assert np.isfinite(lam0).all()
+    for j in (-140, 113):
+        As32 = np.ldexp(A6, j).astype(np.float32)
+        assert np.array_equal(np.ldexp(As32.astype(np.float64), -j), A6)   # exact
+        if j < 0:
+            assert (np.abs(As32[A6 != 0]) < np.finfo(np.float32).tiny).all()
+        lam, V = solve_soa(torch.from_numpy(As32.T.copy()).cuda(), **kw)
+        assert torch.equal(V, V0), j
+        lam = lam.cpu().numpy().astype(np.float64)
+        scaled = np.ldexp(lam0, j)                    # exact in FP64
+        expect = scaled.astype(np.float32).astype(np.float64)
+        if j > 0:
+            assert np.array_equal(lam, expect), j
+        else:
+            exact = expect == scaled
+            assert exact.mean() > 0.01
+            assert np.array_equal(lam[exact], expect[exact])
+            assert np.abs(lam - scaled).max() <= 2.0 ** -149
+
+
 def test_batch_split_over_launches():
     """A batch of more than 2^31 matrices is solved by consecutive launches
     (a dispatch counts its grid in work-items with 32 bits).  FP32 storage,
