@@ -204,17 +204,32 @@ def test_edge_cases():
     assert np.array_equal(lam[3], [-1.0, 2.0, 3.0])
 
 
-def test_nonfinite_inputs_give_nan_only_there():
-    A = gen.normal(1000, 33, "cpu")
+@pytest.mark.parametrize("dtype,refine,vectors", [
+    (torch.float64, True, True), (torch.float64, True, False),
+    (torch.float32, True, True), (torch.float32, False, True),
+    (torch.float32, True, False)],
+    ids=["f64", "f64-vals", "f32r", "f32", "f32r-vals"])
+def test_nonfinite_inputs_give_nan_only_there(dtype, refine, vectors):
+    """A NaN or an infinite entry makes every output of its matrix NaN, in
+    every dtype (FP32 storage widens Inf and NaN exactly), with and without
+    vectors; the other matrices of the batch are untouched: finite, and the
+    same bits as the batch without the bad entries."""
+    A = gen.normal(1000, 33, "cpu").to(dtype)
+    clean = solve_soa(A.cuda(), refine=refine, vectors=vectors)
     A[2, 5] = float("nan")
     A[0, 17] = float("inf")
     A[4, 999] = -float("inf")
-    lam_d, V_d = solve_soa(A.cuda())
+    lam_d, V_d = solve_soa(A.cuda(), refine=refine, vectors=vectors)
+    assert lam_d.dtype == dtype
     lam, V = soa_to_numpy(lam_d, V_d)
     bad = [5, 17, 999]
-    assert np.all(np.isnan(lam[bad])) and np.all(np.isnan(V[bad]))
     good = np.setdiff1d(np.arange(1000), bad)
-    assert np.all(np.isfinite(lam[good])) and np.all(np.isfinite(V[good]))
+    gi = torch.from_numpy(good).cuda()
+    assert np.all(np.isnan(lam[bad])) and np.all(np.isfinite(lam[good]))
+    assert torch.equal(lam_d[:, gi], clean[0][:, gi])
+    if vectors:
+        assert np.all(np.isnan(V[bad])) and np.all(np.isfinite(V[good]))
+        assert torch.equal(V_d[:, gi], clean[1][:, gi])
 
 
 def test_n_zero_and_one():
