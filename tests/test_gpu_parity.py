@@ -125,15 +125,27 @@ def test_newton_on_stress_mix():
     _compare_full(A, flags=s3.FLAG_NEWTON, oflags=oracle.NEWTON, label="newton/stress")
 
 
-def test_layouts_and_modes_agree_bitwise():
+@pytest.mark.parametrize("dtype,kw", [
+    (torch.float64, {}),
+    (torch.float64, {"flags": s3.FLAG_NEWTON}),
+    (torch.float64, {"flags": s3.FLAG_PAPER_BG}),
+    (torch.float32, {}),
+    (torch.float32, {"refine": False}),
+    (torch.float32, {"flags": s3.FLAG_REFINE_CONVERGE})],
+    ids=["f64", "f64-newton", "f64-paper-bg", "f32r", "f32", "f32r-converge"])
+def test_layouts_and_modes_agree_bitwise(dtype, kw):
+    """The eigenvalues are settled before the vectors are formed, and the
+    layouts differ only in how a lane's entries reach it: eigenvalues-only
+    and with vectors, SoA and AoS, give the same bits in every mode."""
     A, _ = gen.stress_mix(70_001, 30, "cpu")
+    A = A.to(dtype)
     Ad = A.cuda()
-    lam_s, V_s = solve_soa(Ad)
-    lam_v, V_v = solve_soa(Ad, vectors=False)
-    assert V_v is None
-    Aa = gen.to_aos(A).cuda()
-    lam_a, V_a = s3.syev3(Aa, layout="aos")
-    lam_av, _ = s3.syev3(Aa, layout="aos", vectors=False)
+    lam_s, V_s = solve_soa(Ad, **kw)
+    lam_v, V_v = solve_soa(Ad, vectors=False, **kw)
+    assert V_v is None and lam_s.dtype == dtype
+    Aa = gen.to_aos(A).contiguous().cuda()
+    lam_a, V_a = s3.syev3(Aa, layout="aos", **kw)
+    lam_av, _ = s3.syev3(Aa, layout="aos", vectors=False, **kw)
     torch.cuda.synchronize()
     assert torch.equal(lam_s, lam_v)
     assert torch.equal(lam_s.t(), lam_a)
