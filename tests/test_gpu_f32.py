@@ -30,7 +30,8 @@ import torch
 import checks
 import oracle
 import paper_1806_06698_amd as s3
-from gpu_common import EPS32, EPS64, need_gpu, soa_to_numpy, solve_soa
+from gpu_common import (EPS32, EPS64, device_measures, need_gpu, sample_indices,
+                        soa_to_numpy, solve_soa)
 from paper_1806_06698_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -191,6 +192,37 @@ def test_scaling_to_the_ends_of_the_float_range(refine, flags):
             assert exact.mean() > 0.01
             assert np.array_equal(lam[exact], expect[exact])
             assert np.abs(lam - scaled).max() <= 2.0 ** -149
+
+
+@pytest.mark.parametrize("refine,flags", [(True, 0), (False, 0),
+                                          (True, s3.FLAG_REFINE_CONVERGE)],
+                         ids=["f32r", "f32", "f32r-converge"])
+def test_full_size_bench_workload(refine, flags):
+    """The FP32-storage forms on the benchmark's batch as it times them: the
+    2^26 SPD matrices (condition <= 1e8, the same seed) rounded to FP32.
+    Every matrix is measured on the device against the refined form's
+    residual and orthogonality bars, a sample against the oracle on the
+    same FP32 inputs widened; the unrefined ablation against its eigenvalue
+    bar, its vectors only reported."""
+    n = 1 << 26
+    print(f"full-size spd_fe FP32 refine={refine} flags={flags} n={n}", flush=True)
+    A32 = gen.spd_fe(n, 2, "cuda").float()
+    lam, V = solve_soa(A32, refine=refine, flags=flags)
+    res, orth = device_measures(A32, lam, V)
+    rmax = res.max().item() / EPS32
+    omax = orth.max().item() / EPS32
+    print(f"  all {n}: max res {rmax:.3f} eps32|A|, max orth {omax:.3f} eps32", flush=True)
+    if refine:
+        assert rmax <= BAR_REFINE["res"] and omax <= BAR_REFINE["orth"]
+    else:
+        assert np.isfinite(rmax) and np.isfinite(omax)
+    it = torch.from_numpy(sample_indices(n, 20_000, 2)).cuda()
+    A6 = A32[:, it].t().double().cpu().numpy()
+    lam_o, _ = oracle.solve(A6)
+    eerr = checks.eig_error(A6, lam[:, it].t().double().cpu().numpy(), lam_o) * (EPS64 / EPS32)
+    print(f"  sample {len(it)} vs oracle: max {eerr.max():.3f} eps32|A|", flush=True)
+    assert eerr.max() <= (BAR_REFINE["lam"] if refine else BAR_UNREFINED_LAM)
+    assert bool(torch.all(lam[1] >= lam[0]).item() and torch.all(lam[2] >= lam[1]).item())
 
 
 def test_batch_split_over_launches():
