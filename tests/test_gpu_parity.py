@@ -338,16 +338,18 @@ def test_full_size(kind, n, seed):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("mode", ["aos", "vals", "newton", "paper_bg"])
-def test_full_size_bench_modes(mode):
-    """The other FP64 modes the benchmark times on its headline batch (2^26
-    SPD matrices, condition <= 1e8, the same seed), at that size: AoS and
-    eigenvalues-only give the SoA result's bits; Newton's method and the
-    paper's own Borges-Gragg iteration meet the bars on every matrix (device
-    measures) and on a sample against the oracle."""
-    n = 1 << 26
-    print(f"full-size spd_fe {mode} n={n}", flush=True)
-    A = gen.spd_fe(n, 2, "cuda")
+@pytest.mark.parametrize("kind,n,seed,mode", [
+    ("spd_fe", 1 << 26, 2, "aos"), ("spd_fe", 1 << 26, 2, "vals"),
+    ("spd_fe", 1 << 26, 2, "newton"), ("spd_fe", 1 << 26, 2, "paper_bg"),
+    ("wide_range", 1 << 28, 4, "aos"), ("wide_range", 1 << 28, 4, "vals")])
+def test_full_size_bench_modes(kind, n, seed, mode):
+    """The other FP64 modes the benchmark times, on its batches (2^26 SPD
+    matrices with condition <= 1e8; 2^28 of the wide-range mix), at their
+    sizes and seeds: AoS and eigenvalues-only give the SoA result's bits;
+    Newton's method and the paper's own Borges-Gragg iteration meet the bars
+    on every matrix (device measures) and on a sample against the oracle."""
+    print(f"full-size {kind} {mode} n={n}", flush=True)
+    A, _ = gen.make(kind, n, seed, "cuda")
     if mode in ("aos", "vals"):
         lam_s, V_s = solve_soa(A)
         if mode == "vals":
@@ -360,6 +362,8 @@ def test_full_size_bench_modes(mode):
             assert torch.equal(lam, lam_s.t())
             del lam, Aa
             assert torch.equal(V, V_s.t().reshape(-1, 3, 3))
+        del lam_s, V_s, V
+        torch.cuda.empty_cache()
         return
     flags = s3.FLAG_NEWTON if mode == "newton" else s3.FLAG_PAPER_BG
     lam, V = solve_soa(A, flags=flags)
@@ -368,7 +372,7 @@ def test_full_size_bench_modes(mode):
     omax = orth.max().item() / EPS64
     print(f"  all {n}: max res {rmax:.2f} eps|A|, max orth {omax:.2f} eps", flush=True)
     assert rmax <= TOL and omax <= TOL
-    it = torch.from_numpy(sample_indices(n, 20_000, 2)).cuda()
+    it = torch.from_numpy(sample_indices(n, 20_000, seed)).cuda()
     A6 = A[:, it].t().cpu().numpy()
     lam_o, _ = oracle.solve(A6)
     e = checks.eig_error(A6, lam[:, it].t().cpu().numpy(), lam_o)
