@@ -250,8 +250,10 @@ typedef struct {
 } syev3_request_buffers;
 
 typedef struct {
-  int64_t submitted, completed, ticks;
-  int64_t matrices_completed;
+  int64_t submitted;
+  int64_t completed;           /* requests done with their results written */
+  int64_t ticks;
+  int64_t matrices_completed;  /* matrices of the completed requests */
   uint64_t pool_bytes_in_use, pool_bytes_peak;
   int64_t acquire_rejections;  /* acquire calls answered SYEV3_E_AGAIN */
   int32_t inflight_ticks_peak;
@@ -259,6 +261,8 @@ typedef struct {
   double busy_seconds;         /* wall time with at least one tick on the GPU */
   int64_t queue_depth;         /* requests submitted and not yet in a tick */
   int64_t queue_depth_peak;
+  int64_t failed;              /* requests done without results (their tick
+                                  could not be launched or did not finish) */
 } syev3_server_stats;
 
 /* Defaults: 64 GiB pool, 4096 slots, 4 ticks in flight, 256 segments/tick,

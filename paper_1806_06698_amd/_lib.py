@@ -66,7 +66,8 @@ class ServerStats(ctypes.Structure):
                 ("segments_per_tick_peak", ctypes.c_int32),
                 ("busy_seconds", ctypes.c_double),
                 ("queue_depth", ctypes.c_int64),
-                ("queue_depth_peak", ctypes.c_int64)]
+                ("queue_depth_peak", ctypes.c_int64),
+                ("failed", ctypes.c_int64)]
 
 
 def lib() -> ctypes.CDLL:

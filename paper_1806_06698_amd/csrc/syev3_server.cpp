@@ -173,8 +173,11 @@ int syev3_server::launch_tick(int slot) {
     tiles += (r.n + syev3::kBlock - 1) / syev3::kBlock;
     r.state = kRunning;
     tk.reqs.push_back(ri);
-    // requests submitted together often share one ready event: wait once
-    if (r.ready && r.ready != last_ready) (void)hipStreamWaitEvent(tk.stream, r.ready, 0);
+    // requests submitted together often share one ready event: wait once.
+    // A wait that cannot be enqueued fails the tick: its input may not be
+    // complete.
+    if (r.ready && r.ready != last_ready && e == hipSuccess)
+      e = hipStreamWaitEvent(tk.stream, r.ready, 0);
     last_ready = r.ready;
     if (r.h_A && e == hipSuccess) {
       const size_t es = r.dtype == SYEV3_F64 ? 8 : 4;
@@ -243,8 +246,12 @@ void syev3_server::scheduler() {
         r.state = kDone;
         r.failed = q != hipSuccess;
         r.t_done = now;
-        st.completed++;
-        st.matrices_completed += r.n;
+        if (r.failed) {
+          st.failed++;
+        } else {
+          st.completed++;
+          st.matrices_completed += r.n;
+        }
         if (track_done) done_ids.push_back(make_id(ri, r.gen));
       }
       tk.reqs.clear();
@@ -269,6 +276,7 @@ void syev3_server::scheduler() {
             req[ri].state = kDone;
             req[ri].failed = true;
             req[ri].t_done = now;
+            st.failed++;
             if (track_done) done_ids.push_back(make_id(ri, req[ri].gen));
           }
           ticks[k].reqs.clear();
