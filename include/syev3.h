@@ -367,6 +367,11 @@ typedef struct {
   uint64_t pool_bytes_peak;
 } syev3_loadgen_result;
 
+/* Runs the load on s (the caller's own requests may share it) and fills
+ * *out.  Returns SYEV3_OK; SYEV3_E_N for options out of range; SYEV3_E_HIP if
+ * a copy, an event or a tick failed (the run stops at the first error, and
+ * every request it admitted is waited for and released before the return);
+ * SYEV3_E_NOMEM if host memory runs out. */
 int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* opts,
                          syev3_loadgen_result* out);
 

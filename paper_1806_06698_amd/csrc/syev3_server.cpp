@@ -677,10 +677,10 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
           int slot;
           Request* r = lookup(s, id, &slot);
           if (!r || r->state != kAdmitted) { rc = SYEV3_E_STATE; break; }
+          s->queue.push_back(slot);  // may throw: the request stays admitted
           r->state = kQueued;
           r->ready = ev;
           r->t_submit = ts;
-          s->queue.push_back(slot);
           s->note_queue();
           s->st.submitted++;
         }
@@ -741,6 +741,14 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
       for (int64_t id : done) {
         auto it = live.find(id);
         if (it == live.end()) continue;
+        // a request whose tick failed ends the run with that error
+        const int q = syev3_server_poll(s, id, nullptr);
+        if (q != 1) {
+          if (rc == SYEV3_OK) rc = q < 0 ? q : SYEV3_E_STATE;
+          (void)syev3_server_release(s, id);
+          live.erase(it);
+          continue;
+        }
         lat.push_back(tnow - it->second.t_arrival);
         last_done = tnow;
         out->matrices += it->second.n;
