@@ -99,17 +99,18 @@ class Request:
         self.dtype = bufs.dtype
         tdt = torch.float64 if bufs.dtype == _lib.F64 else torch.float32
         es = 8 if tdt == torch.float64 else 4
-        self.A = _tensor_at(bufs.A, (6, bufs.n), tdt, es)
-        self.lam = _tensor_at(bufs.lam, (3, bufs.n), tdt, es)
-        self.V = _tensor_at(bufs.V, (9, bufs.n), tdt, es) if bufs.V else None
+        dev = server.device
+        self.A = _tensor_at(bufs.A, (6, bufs.n), tdt, es, dev)
+        self.lam = _tensor_at(bufs.lam, (3, bufs.n), tdt, es, dev)
+        self.V = _tensor_at(bufs.V, (9, bufs.n), tdt, es, dev) if bufs.V else None
         self.ready_event = None  # held from submit to release
         self.host_buffers = None  # likewise, for host-staged requests
 
 
-def _tensor_at(ptr, shape, dtype, esize):
-    """A torch view of device memory owned by the server (no copy)."""
+def _tensor_at(ptr, shape, dtype, esize, dev):
+    """A torch view of memory owned by the server on device `dev` (no
+    copy)."""
     numel = shape[0] * shape[1]
-    dev = torch.cuda.current_device()
     class _Holder:
         __cuda_array_interface__ = {
             "shape": shape, "typestr": "<f8" if esize == 8 else "<f4",
@@ -132,6 +133,9 @@ class Server:
         o.grid_blocks = grid_blocks
         o.use_graphs = 1 if use_graphs else 0
         h = ctypes.c_void_p()
+        # the server lives on the device current now: its pool, streams and
+        # requests' tensors
+        self.device = torch.cuda.current_device()
         _lib.check(self.L.syev3_server_create(ctypes.byref(o), ctypes.byref(h)),
                    "syev3_server_create")
         self.h = h
