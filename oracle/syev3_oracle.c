@@ -37,6 +37,13 @@
  *     them (stable for ties); no sign normalisation.
  *   - Non-finite input gives NaN eigenvalues and eigenvectors.
  *
+ * Parity unpinned: the iteration counts it reports (the paper prints none)
+ * and the identity of each eigenvector, i.e. its sign and the basis chosen
+ * inside a repeated eigenvalue's eigenspace (several results are correct).
+ * The eigenvalues, the two accuracy measures of Sec. 1.5 and every step's
+ * output are pinned by the tests: closed forms, invariants, LAPACK, cyclic
+ * Jacobi and the paper's stated bounds.
+ *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math (no contraction, so the
  * result does not depend on FMA formation).
  */
