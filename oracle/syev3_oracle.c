@@ -40,9 +40,11 @@
  * Parity unpinned: the iteration counts it reports (the paper prints none)
  * and the identity of each eigenvector, i.e. its sign and the basis chosen
  * inside a repeated eigenvalue's eigenspace (several results are correct).
- * The eigenvalues, the two accuracy measures of Sec. 1.5 and every step's
- * output are pinned by the tests: closed forms, invariants, LAPACK, cyclic
- * Jacobi and the paper's stated bounds.
+ * What the tests pin: the arrow reduction (interlacing), the exact
+ * deflations, the zero finder's root (the largest eigenvalue of the reduced
+ * arrow), the eigenvalues, the two accuracy measures of Sec. 1.5 and the
+ * Sec. 1.3 orthogonality bound, against closed forms, invariants, LAPACK
+ * and cyclic Jacobi.
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math (no contraction, so the
  * result does not depend on FMA formation).
