@@ -32,7 +32,22 @@ def main(path):
                                flags, ip(), 1)
         return lam, V
 
+    def branches(A, flags):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        lam = np.empty((A.shape[0], 3))
+        V = np.empty((A.shape[0], 3, 3))
+        info = np.empty((A.shape[0], 4), dtype=np.int32)
+        lib.oracle_solve_batch(A.shape[0], A.ctypes.data_as(dp),
+                               lam.ctypes.data_as(dp), V.ctypes.data_as(dp),
+                               flags, info.ctypes.data_as(ip), 1)
+        return info[:, 0].tolist()
+
     fails = []
+    # the deflation tests and the h guard decide as their inequalities state
+    from deflation_cases import DEFLATION_BRANCHES, DEFLATION_CASES
+    for flags, want in DEFLATION_BRANCHES.items():
+        if branches(DEFLATION_CASES, flags) != want:
+            fails.append(f"deflation-branches/flags={flags}")
     for kind, seed, n in (("stress_mix", 1, 3000), ("normal", 0, 2000),
                           ("wide_range", 4, 1000), ("spd_fe", 2, 1000)):
         A = gen.to_aos(gen.make(kind, n, seed)[0]).numpy()

@@ -14,6 +14,7 @@ import torch
 
 import checks
 import oracle
+from deflation_cases import DEFLATION_BRANCHES, DEFLATION_CASES
 import paper_1806_06698_amd as s3
 from gpu_common import (EPS64, device_measures, need_gpu, sample_indices,
                         soa_to_numpy, solve_soa)
@@ -118,6 +119,28 @@ def test_paper_zero_finder_takes_the_oracles_steps():
           flush=True)
     assert agree > 0.95 and abs(it.mean() - it_o.mean()) < 0.01
     assert it.mean() > 2.0 * it_d.mean()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_deflation_and_h_tests_decide_as_stated(dtype):
+    """On matrices where the EISPACK and the simplified deflation tests, and
+    the h guard, decide differently (Sec. 1.1), every flag combination takes
+    the branch the inequalities give (the oracle's pinned table), in FP64 and
+    in FP32 storage (the test is FP64 in both), and meets the bars against
+    the oracle."""
+    A6 = DEFLATION_CASES.astype(np.float32 if dtype == torch.float32 else np.float64)
+    A = torch.from_numpy(np.ascontiguousarray(A6.T)).cuda()
+    A64 = A6.astype(np.float64)
+    eps = EPS64 if dtype == torch.float64 else 2.0 ** -23
+    for flags, want in DEFLATION_BRANCHES.items():
+        lam, V, info = solve_soa(A, flags=flags, info=True)
+        assert ((info.cpu().numpy() & 0xFF).tolist()) == want, flags
+        lam_o, _ = oracle.solve(A64, flags=flags)
+        l = lam.t().double().cpu().numpy()
+        W = V.t().double().cpu().numpy().reshape(-1, 3, 3)
+        assert checks.eig_error(A64, l, lam_o).max() * EPS64 <= TOL * eps
+        assert checks.residual(A64, l, W).max() * EPS64 <= TOL * eps
+        assert checks.orthogonality(W).max() * EPS64 <= TOL * eps
 
 
 def test_newton_on_stress_mix():

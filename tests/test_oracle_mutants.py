@@ -71,6 +71,12 @@ MUTANTS = {
          "u[0] = v0; u[1] = v1; u[2] = v2;"),
     "Newton step sign":
         ("double xn = x - f / fp;", "double xn = x + f / fp;"),
+    "simplified deflation bound uses alpha1 - alpha2":
+        ("rhs = C_DEFL * EPS * fabs(al1 + al2) * h * h;",
+         "rhs = C_DEFL * EPS * fabs(al1 - al2) * h * h;"),
+    "h guard applied only when it is switched off":
+        ("if (!diagonal && !(flags & ORACLE_NO_H_GUARD))",
+         "if (!diagonal && (flags & ORACLE_NO_H_GUARD))"),
 }
 
 

@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import checks
+from deflation_cases import DEFLATION_BRANCHES, DEFLATION_CASES
 from paper_1806_06698_amd import gen
 
 EPS = 2.0 ** -52
@@ -95,6 +96,22 @@ def test_combo_deflation_is_exact(oracle_mod):
     assert np.all((lam == A[:, [0]]).any(axis=1))
     assert checks.residual(A, lam, V).max() <= TOL
     assert checks.orthogonality(V).max() <= TOL
+
+
+
+
+def test_deflation_and_h_tests_decide_as_stated(oracle_mod):
+    """Each deflation test and the h guard take the branch that the stated
+    inequality gives, with margins of a factor 20 or more; every branch
+    gives eigenvalues within 1 eps ||A|| of LAPACK's."""
+    A = DEFLATION_CASES
+    ref = checks.lapack_eigvals(A)
+    for flags, want in DEFLATION_BRANCHES.items():
+        lam, V, info = oracle_mod.solve(A, flags=flags, return_info=True)
+        assert info[:, 0].tolist() == want, flags
+        assert checks.eig_error(A, lam, ref).max() <= 1.0
+        assert checks.residual(A, lam, V).max() <= TOL
+        assert checks.orthogonality(V).max() <= TOL
 
 
 def test_zero_and_scalar_identity(oracle_mod):
