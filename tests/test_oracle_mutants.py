@@ -77,6 +77,17 @@ MUTANTS = {
     "h guard applied only when it is switched off":
         ("if (!diagonal && !(flags & ORACLE_NO_H_GUARD))",
          "if (!diagonal && (flags & ORACLE_NO_H_GUARD))"),
+    "Newton starts from the two-pole model (right of the root)":
+        ("    x = g2 + sqrt(g2 * g2 + b1 * b1);\n  else\n    x = b1 * b1 / (-g2 + sqrt(g2 * g2 + b1 * b1));",
+         "    x = g2 + sqrt(g2 * g2 + b1 * b1 + b2 * b2);\n  else\n    x = (b1 * b1 + b2 * b2) / (-g2 + sqrt(g2 * g2 + b1 * b1 + b2 * b2));"),
+    "vectors not permuted with the sorted eigenvalues":
+        ("V[3 * r + c] = W[ord[c]][r];", "V[3 * r + c] = W[c][r];"),
+    "d2 drops a term":
+        ("d2 = (al1 * be1 * be1 + al2 * be2 * be2) / (h * h);",
+         "d2 = (al1 * be1 * be1) / (h * h);"),
+    "back-transform row 2 uses the wrong rotation entry":
+        ("W[c][1] = J[2] * U[c][0] + J[3] * U[c][1];",
+         "W[c][1] = J[1] * U[c][0] + J[3] * U[c][1];"),
 }
 
 
