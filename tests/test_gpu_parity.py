@@ -174,6 +174,14 @@ def test_layouts_and_modes_agree_bitwise(dtype, kw):
     assert torch.equal(lam_s.t(), lam_a)
     assert torch.equal(lam_s.t(), lam_av)
     assert torch.equal(V_s.t().reshape(-1, 3, 3), V_a)
+    # the kernels that also write the per-matrix info word give the same
+    # results, and the same info in either layout
+    lam_i, V_i, inf_s = solve_soa(Ad, info=True, **kw)
+    lam_ai, V_ai, inf_a = s3.syev3(Aa, layout="aos", info=True, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(lam_i, lam_s) and torch.equal(V_i, V_s)
+    assert torch.equal(lam_ai, lam_a) and torch.equal(V_ai, V_a)
+    assert torch.equal(inf_s, inf_a)
 
 
 def test_plane_stride_larger_than_n():
