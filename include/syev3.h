@@ -310,7 +310,8 @@ int syev3_server_submit_host(syev3_server* s, int64_t request, const void* host_
  * in seconds. */
 int syev3_server_poll(syev3_server* s, int64_t request, double* latency_s);
 
-/* Block until the request completes or timeout_s passes (< 0: no limit).
+/* Block until the request completes or timeout_s passes (< 0, or above 1e9
+ * seconds: no limit; NaN: SYEV3_E_N).
  * Returns 1 when complete, SYEV3_E_TIMEOUT, SYEV3_E_HIP if its tick failed,
  * or SYEV3_E_STATE if the id is stale, which includes a release of the
  * request by another thread during the wait. */
@@ -336,10 +337,13 @@ int syev3_server_get_stats(syev3_server* s, syev3_server_stats* out);
  * scheduler's observation of the tick's completion event.
  */
 typedef struct {
-  double qps;            /* > 0: open loop (Poisson); 0: closed loop */
-  int32_t closed_concurrency; /* closed loop: requests kept in flight */
-  double duration_s;
-  double max_log2_n;
+  double qps;            /* > 0 (at most 1e8): open loop (Poisson); 0: closed
+                            loop */
+  int32_t closed_concurrency; /* closed loop: requests kept in flight,
+                                  1 to 2^20 */
+  double duration_s;     /* > 0, at most 1e6; open loop: qps * duration_s at
+                            most 1e8 arrivals */
+  double max_log2_n;     /* 0 to 40 */
   double frac_f32;
   uint64_t seed;
   const void* src_f64;   /* 6 planes of src_n doubles (device, or pinned

@@ -524,6 +524,10 @@ int syev3_server_poll(syev3_server* s, int64_t id, double* latency_s) {
 
 int syev3_server_wait(syev3_server* s, int64_t id, double timeout_s, double* latency_s) {
   if (!s) return SYEV3_E_STATE;
+  if (std::isnan(timeout_s)) return SYEV3_E_N;
+  // a limit beyond any real wait (and beyond what a clock duration holds)
+  // is no limit
+  const bool unlimited = timeout_s < 0 || timeout_s > 1e9;
   std::unique_lock<std::mutex> lk(s->mu);
   Request* r = lookup(s, id, nullptr);
   if (!r || r->state == kAdmitted) return SYEV3_E_STATE;
@@ -531,7 +535,7 @@ int syev3_server_wait(syev3_server* s, int64_t id, double timeout_s, double* lat
   // slot may be acquired again): that ends the wait with E_STATE
   const uint32_t gen = r->gen;
   auto done = [&] { return r->gen != gen || r->state == kDone; };
-  if (timeout_s < 0) {
+  if (unlimited) {
     s->cv_done.wait(lk, done);
   } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
     return SYEV3_E_TIMEOUT;
@@ -570,8 +574,14 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
                          syev3_loadgen_result* out) {
   if (!s || !o || !out) return SYEV3_E_NULL;
   const bool closed = o->qps == 0.0;
-  if (!(o->qps >= 0) || (closed && o->closed_concurrency < 1) || !(o->duration_s > 0) ||
+  // The limits keep every quantity representable and the host-side queue of
+  // arrivals bounded: at most 1e8 open-loop arrivals (1e8 per second) or
+  // 2^20 closed-loop requests in flight, requests of at most 2^40 matrices.
+  if (!(o->qps >= 0) || !(o->qps <= 1e8) || (closed && o->closed_concurrency < 1) ||
+      (closed && o->closed_concurrency > (1 << 20)) || !(o->duration_s > 0) ||
+      !(o->duration_s <= 1e6) || (!closed && !(o->qps * o->duration_s <= 1e8)) ||
       o->src_n < 1 || !o->src_f64 || !o->src_f32 || !(o->max_log2_n >= 0) ||
+      !(o->max_log2_n <= 40) ||
       (o->host_staged && (!o->sink || std::exp2(o->max_log2_n) > (double)o->src_n)))
     return SYEV3_E_N;
   std::memset(out, 0, sizeof(*out));
@@ -637,8 +647,8 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
   auto draw = [&](double t) {
     Arrival a;
     a.t = t;
-    a.n = std::max<int64_t>(
-        1, std::min<int64_t>(o->src_n, (int64_t)std::floor(std::exp2(U(rng) * o->max_log2_n))));
+    const double nd = std::floor(std::exp2(U(rng) * o->max_log2_n));
+    a.n = std::max<int64_t>(1, (int64_t)std::min((double)o->src_n, nd));
     a.dtype = U(rng) < o->frac_f32 ? SYEV3_F32_REFINE : SYEV3_F64;
     return a;
   };

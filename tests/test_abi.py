@@ -125,6 +125,37 @@ def test_python_binding_refuses_cpu_tensors():
         s3.syev3(torch.zeros(6, 4, dtype=torch.float64))
 
 
+def test_loadgen_and_wait_options_are_range_checked(L, no_device):
+    """Options out of range are refused (SYEV3_E_N) before the server is
+    touched: a NaN or oversized rate, a duration or an arrival count too
+    large to represent or queue, a request size exponent above 40, a
+    closed-loop concurrency outside 1..2^20, and a NaN wait timeout.  Each
+    case breaks one option of an otherwise valid set; the server handle is a
+    fake address that the checks never reach."""
+    from paper_1806_06698_amd import serve
+    serve._bind(L)
+    fake = ctypes.c_void_p(1 << 40)
+
+    def opts(**kw):
+        o = serve.LoadgenOpts(qps=1000.0, closed_concurrency=0, duration_s=1.0,
+                              max_log2_n=10.0, frac_f32=0.5, seed=0, src_f64=1 << 41,
+                              src_f32=1 << 42, src_n=1024, want_vectors=1, host_staged=0,
+                              sink=None)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return o
+
+    bad = [dict(qps=2e8), dict(qps=float("nan")), dict(qps=1e6, duration_s=1000.0),
+           dict(qps=1.0, duration_s=2e6), dict(duration_s=0.0), dict(max_log2_n=41.0),
+           dict(max_log2_n=float("inf")), dict(qps=0.0, closed_concurrency=(1 << 20) + 1),
+           dict(qps=0.0, closed_concurrency=0)]
+    for kw in bad:
+        r = serve.LoadgenResult()
+        assert L.syev3_server_loadgen(fake, ctypes.byref(opts(**kw)), ctypes.byref(r)) == -1, kw
+    lat = ctypes.c_double()
+    assert L.syev3_server_wait(fake, 0, float("nan"), ctypes.byref(lat)) == -1
+
+
 def test_server_rejects_bad_options_without_a_gpu(L):
     from paper_1806_06698_amd import _lib as lb
     o = lb.ServerOpts()
