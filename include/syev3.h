@@ -237,7 +237,8 @@ typedef struct {
   int32_t max_inflight_ticks;  /* ticks on the GPU at once (streams), 1 .. 64 */
   int32_t max_segments_per_tick; /* requests per tick,
                                     1 .. SYEV3_SERVER_MAX_SEGMENTS */
-  int32_t grid_blocks;         /* blocks of the persistent kernel; 0 = auto */
+  int32_t grid_blocks;         /* blocks of the persistent kernel, at most
+                                  2^24; 0 = auto (8 per compute unit) */
   int32_t use_graphs;          /* 1: launch ticks through captured graphs */
 } syev3_server_opts;
 

@@ -368,7 +368,8 @@ int syev3_server_create(const syev3_server_opts* opts, syev3_server** out) {
   if (o.hbm_budget_bytes < kAlign || o.max_requests < 1 ||
       o.max_requests > SYEV3_SERVER_MAX_REQUESTS || o.max_inflight_ticks < 1 ||
       o.max_inflight_ticks > 64 || o.max_segments_per_tick < 1 ||
-      o.max_segments_per_tick > syev3::kMaxSegmentsPerTick || o.grid_blocks < 0)
+      o.max_segments_per_tick > syev3::kMaxSegmentsPerTick || o.grid_blocks < 0 ||
+      o.grid_blocks > (1 << 24))
     return SYEV3_E_N;
   syev3_server* s = nullptr;
   int rc = SYEV3_OK;

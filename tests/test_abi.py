@@ -167,6 +167,11 @@ def test_server_rejects_bad_options_without_a_gpu(L):
     L.syev3_server_default_opts(ctypes.byref(o))
     o.max_segments_per_tick = 100000
     assert L.syev3_server_create(ctypes.byref(o), ctypes.byref(h)) == -1
+    L.syev3_server_default_opts(ctypes.byref(o))
+    o.grid_blocks = (1 << 24) + 1
+    assert L.syev3_server_create(ctypes.byref(o), ctypes.byref(h)) == -1
+    o.grid_blocks = -1
+    assert L.syev3_server_create(ctypes.byref(o), ctypes.byref(h)) == -1
     assert L.syev3_server_create(ctypes.byref(o), None) == -2
     b = lb.RequestBuffers()
     assert L.syev3_server_acquire(None, 10, 0, 1, ctypes.byref(b)) == -2
