@@ -235,7 +235,8 @@ def bench(duration_s=4.0, budget_bytes=64 << 30, seed=3):
     """Serving measurement: request sizes 2^U(0,20) from the stress mix, 50%
     FP64 / 50% FP32-storage.  First the saturated rate (closed loop, 64
     requests in flight), then open-loop Poisson arrivals at 50% and 80% of
-    that rate."""
+    that rate, and at a low fixed rate (2000 requests/s, about one request
+    per tick: the latency floor of the path)."""
     from . import gen
     src_n = 1 << 20
     A, _ = gen.stress_mix(src_n, seed=seed, device="cuda")
@@ -255,6 +256,9 @@ def bench(duration_s=4.0, budget_bytes=64 << 30, seed=3):
             r = srv.loadgen(A, Af, qps=rho * rate, duration_s=duration_s, seed=seed + 1)
             r["offered_qps"] = rho * rate
             out[f"open_loop_{int(rho * 100)}pct"] = r
+        r = srv.loadgen(A, Af, qps=2000.0, duration_s=min(1.0, duration_s), seed=seed + 3)
+        r["offered_qps"] = 2000.0
+        out["open_loop_2000qps"] = r
         # host-staged: inputs from pinned host memory, results back to it
         m = 1 << 20
         hA = A[:, :m].cpu().contiguous().pin_memory()
