@@ -184,6 +184,45 @@ def test_layouts_and_modes_agree_bitwise(dtype, kw):
     assert torch.equal(inf_s, inf_a)
 
 
+def test_calls_from_several_threads_on_their_own_streams():
+    """The entry points keep no mutable global state: four host threads, each
+    on its own stream, repeatedly solve different modes (FP64 SoA, FP32
+    storage, AoS, Newton) at once, and every result equals, bitwise, the
+    same call made alone beforehand."""
+    import threading
+    A, _ = gen.stress_mix(60_001, 39, "cpu")
+    cases = [(A.cuda(), {}),
+             (A.float().cuda(), {}),
+             (gen.to_aos(A).cuda(), {"layout": "aos"}),
+             (A.cuda(), {"flags": s3.FLAG_NEWTON})]
+    ref = []
+    for X, kw in cases:
+        lam, V = s3.syev3(X, **kw)
+        torch.cuda.synchronize()
+        ref.append((lam.clone(), V.clone()))
+    errors = []
+
+    def work(k):
+        X, kw = cases[k]
+        st = torch.cuda.Stream()
+        try:
+            for _ in range(20):
+                lam, V = s3.syev3(X, stream=st, **kw)
+                st.synchronize()
+                if not (torch.equal(lam, ref[k][0]) and torch.equal(V, ref[k][1])):
+                    errors.append(k)
+                    return
+        except Exception as exc:  # reported below
+            errors.append(repr(exc))
+
+    th = [threading.Thread(target=work, args=(k,)) for k in range(len(cases))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+
+
 def test_plane_stride_larger_than_n():
     A, _ = gen.stress_mix(50_000, 31, "cpu")
     buf = torch.full((6, 65_536), float("nan"), dtype=torch.float64)
