@@ -298,9 +298,9 @@ int syev3_server_submit(syev3_server* s, int64_t request, hipEvent_t ready);
 /* Host-staged submission: the request's input is copied from host memory
  * host_A (6 planes of n, SoA, the request's dtype) to its device buffer
  * before its tick, and the outputs are copied back to host_lambda (3 x n)
- * and host_V (9 x n, or NULL) after it.  The copies run on per-slot copy
- * streams apart from the compute streams, so one tick's copies overlap
- * other ticks' kernels.  The host memory must stay valid and untouched until
+ * and host_V (9 x n, or NULL) after it.  The copies run in order on the
+ * tick's own stream, before and after its kernel; ticks run on separate
+ * streams, so one tick's copies overlap other ticks' kernels.  The host memory must stay valid and untouched until
  * the request completes; it should be pinned (hipHostMalloc), otherwise the
  * copies do not overlap.  Completion (poll/wait) includes the copy back. */
 int syev3_server_submit_host(syev3_server* s, int64_t request, const void* host_A,

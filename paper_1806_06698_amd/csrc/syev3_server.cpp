@@ -72,11 +72,14 @@ struct Request {
 };
 
 struct TickSlot {
+  // A tick runs in order on its own stream: the host-staged inputs' copies,
+  // the table copy and the kernel, the copies of host-staged results, then
+  // its completion event.  Ticks overlap one another (one tick's copies with
+  // another's kernel) because each slot has its own stream.  Copy streams of
+  // their own per slot had only multiplied the streams sharing the process's
+  // few hardware queues: host-staged throughput at 4 slots was about half of
+  // that at 2.
   hipStream_t stream = nullptr;
-  hipStream_t copy_in = nullptr;   // host-staged inputs
-  hipStream_t copy_out = nullptr;  // host-staged outputs
-  hipEvent_t in_done = nullptr;
-  hipEvent_t kernel_done = nullptr;
   hipEvent_t done = nullptr;
   syev3::TickTable* h_table = nullptr;  // pinned host
   syev3::TickTable* d_table = nullptr;  // device
@@ -154,7 +157,7 @@ int syev3_server::launch_tick(int slot) {
   syev3::TickTable* t = tk.h_table;
   int nseg = 0;
   int64_t tiles = 0;
-  bool staged_in = false, staged_out = false;
+  bool staged_out = false;
   hipError_t e = hipSuccess;
   hipEvent_t last_ready = nullptr;
   tk.reqs.clear();
@@ -181,17 +184,12 @@ int syev3_server::launch_tick(int slot) {
     last_ready = r.ready;
     if (r.h_A && e == hipSuccess) {
       const size_t es = r.dtype == SYEV3_F64 ? 8 : 4;
-      e = hipMemcpyAsync(r.A, r.h_A, 6 * (size_t)r.n * es, hipMemcpyHostToDevice, tk.copy_in);
-      staged_in = true;
+      e = hipMemcpyAsync(r.A, r.h_A, 6 * (size_t)r.n * es, hipMemcpyHostToDevice, tk.stream);
     }
     if (r.h_lam) staged_out = true;
   }
   t->nseg = nseg;
   t->total_tiles = tiles;
-  if (staged_in && e == hipSuccess) {
-    e = hipEventRecord(tk.in_done, tk.copy_in);
-    if (e == hipSuccess) e = hipStreamWaitEvent(tk.stream, tk.in_done, 0);
-  }
   if (e == hipSuccess) {
     if (tk.exec) {
       e = hipGraphLaunch(tk.exec, tk.stream);
@@ -203,23 +201,19 @@ int syev3_server::launch_tick(int slot) {
     }
   }
   if (staged_out && e == hipSuccess) {
-    // results back on the copy-out stream; the tick completes after them
-    e = hipEventRecord(tk.kernel_done, tk.stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(tk.copy_out, tk.kernel_done, 0);
+    // results back to the host; the tick completes after them
     for (int ri : tk.reqs) {
       const Request& r = req[ri];
       if (!r.h_lam || e != hipSuccess) continue;
       const size_t es = r.dtype == SYEV3_F64 ? 8 : 4;
       e = hipMemcpyAsync(r.h_lam, r.lam, 3 * (size_t)r.n * es, hipMemcpyDeviceToHost,
-                         tk.copy_out);
+                         tk.stream);
       if (e == hipSuccess && r.h_V && r.vecs)
         e = hipMemcpyAsync(r.h_V, r.V, 9 * (size_t)r.n * es, hipMemcpyDeviceToHost,
-                           tk.copy_out);
+                           tk.stream);
     }
-    if (e == hipSuccess) e = hipEventRecord(tk.done, tk.copy_out);
-  } else if (e == hipSuccess) {
-    e = hipEventRecord(tk.done, tk.stream);
   }
+  if (e == hipSuccess) e = hipEventRecord(tk.done, tk.stream);
   if (e != hipSuccess) return SYEV3_E_HIP;
   tk.range = roctxRangeStartA("syev3 tick");
   tk.busy = true;
@@ -267,10 +261,7 @@ void syev3_server::scheduler() {
           // The tick's requests complete as failed; the slot stays idle.
           // Copies enqueued before the failure may still write into their
           // buffers: let them finish before the buffers can be released.
-          TickSlot& tk = ticks[k];
-          (void)hipStreamSynchronize(tk.copy_in);
-          (void)hipStreamSynchronize(tk.stream);
-          (void)hipStreamSynchronize(tk.copy_out);
+          (void)hipStreamSynchronize(ticks[k].stream);
           const auto now = Clock::now();
           for (int ri : ticks[k].reqs) {
             req[ri].state = kDone;
@@ -319,10 +310,6 @@ int syev3_server::init(const syev3_server_opts& opts) {
   for (auto& tk : ticks) {
     tk.reqs.reserve(o.max_segments_per_tick);
     if (hipStreamCreateWithFlags(&tk.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&tk.copy_in, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&tk.copy_out, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&tk.in_done, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&tk.kernel_done, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&tk.done, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc((void**)&tk.h_table, table_bytes, hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&tk.d_table, table_bytes) != hipSuccess)
@@ -401,17 +388,11 @@ int syev3_server_destroy(syev3_server* s) {
   }
   for (auto& tk : s->ticks) {
     if (tk.stream) (void)hipStreamSynchronize(tk.stream);
-    if (tk.copy_in) (void)hipStreamSynchronize(tk.copy_in);
-    if (tk.copy_out) (void)hipStreamSynchronize(tk.copy_out);
     if (tk.exec) (void)hipGraphExecDestroy(tk.exec);
     if (tk.graph) (void)hipGraphDestroy(tk.graph);
     if (tk.d_table) (void)hipFree(tk.d_table);
     if (tk.h_table) (void)hipHostFree(tk.h_table);
     if (tk.done) (void)hipEventDestroy(tk.done);
-    if (tk.kernel_done) (void)hipEventDestroy(tk.kernel_done);
-    if (tk.in_done) (void)hipEventDestroy(tk.in_done);
-    if (tk.copy_out) (void)hipStreamDestroy(tk.copy_out);
-    if (tk.copy_in) (void)hipStreamDestroy(tk.copy_in);
     if (tk.stream) (void)hipStreamDestroy(tk.stream);
   }
   if (s->pool) (void)hipFree(s->pool);
