@@ -111,7 +111,13 @@ extern "C" {
                                      them, for one or two more FP64
                                      evaluations per root; SYEV3_F32_REFINE
                                      only */
-#define SYEV3_FLAGS_ALL 31u
+#define SYEV3_FLAG_NO_SCALE 32u   /* no power-of-two scaling of each matrix
+                                     (the paper has none): for measuring
+                                     what the scaling costs.  Matrices whose
+                                     entries lie outside about 2^-500 ..
+                                     2^+300 may then lose accuracy or
+                                     overflow */
+#define SYEV3_FLAGS_ALL 63u
 
 /* error codes */
 #define SYEV3_OK 0
@@ -284,18 +290,36 @@ int syev3_server_destroy(syev3_server* s);
 
 /* Admit a request of n matrices (vals+vecs if want_vectors) of dtype.
  * Returns a request id >= 0 and fills *bufs, or SYEV3_E_AGAIN if the pool or
- * the slots are full now, or SYEV3_E_BUDGET if it can never fit. */
+ * the slots are full now, or SYEV3_E_BUDGET if it can never fit,
+ * SYEV3_E_NOMEM if host memory for the pool's bookkeeping runs out (nothing
+ * is admitted then). */
 int64_t syev3_server_acquire(syev3_server* s, int64_t n, int dtype,
                              int want_vectors, syev3_request_buffers* bufs);
 
+/* Admit a request whose input stays where the caller keeps it: A is device
+ * memory holding 6 planes of n entries with plane stride lda >= n (SoA, the
+ * request's dtype), read by the request's tick and not copied.  Only the
+ * outputs take pool memory (bufs->lambda, bufs->V: planes of n); bufs->A is
+ * A.  The caller keeps A valid and unchanged until the request is done.
+ * Submit it with syev3_server_submit (not syev3_server_submit_host).
+ * SYEV3_E_NULL for a NULL A, SYEV3_E_LAYOUT for lda < n; otherwise as
+ * syev3_server_acquire. */
+int64_t syev3_server_acquire_view(syev3_server* s, int64_t n, int dtype,
+                                  int want_vectors, const void* A, int64_t lda,
+                                  syev3_request_buffers* bufs);
+
 /* Queue an admitted request for the next tick.  Its A must be complete
  * when `ready` (a hipEvent_t, or NULL) has completed: the tick waits for it
- * on the device, the host does not block.  The wait is enqueued when the
- * tick is launched, not here, so `ready` must stay valid (not destroyed)
- * and must not be recorded again until the request is reported done. */
+ * on the device, the host does not block.  The wait on `ready` is enqueued
+ * here, on a stream of the server, behind which the server records an event
+ * of its own that the tick waits on; so once this call returns the caller
+ * may destroy `ready` or record it again.  NULL: A is complete now.
+ * SYEV3_E_HIP if the wait could not be enqueued (the request stays admitted
+ * and may be submitted again). */
 int syev3_server_submit(syev3_server* s, int64_t request, hipEvent_t ready);
 
-/* Host-staged submission: the request's input is copied from host memory
+/* Host-staged submission (not for a request admitted as a view, which gives
+ * SYEV3_E_STATE): the request's input is copied from host memory
  * host_A (6 planes of n, SoA, the request's dtype) to its device buffer
  * before its tick, and the outputs are copied back to host_lambda (3 x n)
  * and host_V (9 x n, or NULL) after it.  The copies run in order on the
@@ -319,7 +343,9 @@ int syev3_server_poll(syev3_server* s, int64_t request, double* latency_s);
 int syev3_server_wait(syev3_server* s, int64_t request, double timeout_s,
                       double* latency_s);
 
-/* Return the request's buffers to the pool (after it completed). */
+/* Return the request's buffers to the pool (after it completed).
+ * SYEV3_E_NOMEM if host memory for the pool's bookkeeping runs out; the
+ * request is then still held, and the call may be repeated. */
 int syev3_server_release(syev3_server* s, int64_t request);
 
 int syev3_server_get_stats(syev3_server* s, syev3_server_stats* out);
@@ -358,6 +384,10 @@ typedef struct {
                             which every request overwrites */
   void* sink;            /* host_staged: pinned host memory of at least
                             12 * 2^max_log2_n * 8 bytes for the results */
+  int32_t input_views;   /* 1 (device sources only): each request reads its
+                            window of the source pool in place
+                            (syev3_server_acquire_view); nothing is copied
+                            and only the outputs take pool memory */
 } syev3_loadgen_opts;
 
 typedef struct {

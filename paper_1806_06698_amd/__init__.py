@@ -17,12 +17,14 @@ import torch
 
 from . import _lib
 from ._lib import (AOS, AOS9, F32, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD,
-                   FLAG_PAPER_BG, FLAG_REFINE_CONVERGE, FLAG_SIMPLIFIED_DEFLATION, SOA,
+                   FLAG_NO_SCALE, FLAG_PAPER_BG, FLAG_REFINE_CONVERGE,
+                   FLAG_SIMPLIFIED_DEFLATION, SOA,
                    Syev3Error)
 
 __all__ = ["syev3", "syev3_inplace", "batched_syev3", "batched_syev3_ex", "batched_syev3_info",
            "F64", "F32_REFINE", "F32", "SOA", "AOS", "AOS9", "FLAG_SIMPLIFIED_DEFLATION",
-           "FLAG_NO_H_GUARD", "FLAG_NEWTON", "FLAG_PAPER_BG", "FLAG_REFINE_CONVERGE", "Syev3Error",
+           "FLAG_NO_H_GUARD", "FLAG_NEWTON", "FLAG_PAPER_BG", "FLAG_REFINE_CONVERGE", "FLAG_NO_SCALE",
+           "Syev3Error",
            "lib_path"]
 
 lib_path = _lib.LIB_PATH
@@ -80,6 +82,24 @@ def _check_out(t, shape, strides, A, name):
                          f"{tuple(t.stride())}, {t.dtype}, {t.device}")
 
 
+def _soa_geometry(A):
+    """(n, ld) of an SoA input: shape (6, n), unit column stride and a plane
+    stride ld >= n, so that the 6 planes are disjoint runs of n elements (a
+    broadcast or overlapping view would make the kernels read and write
+    past the storage the outputs are sized from)."""
+    if A.dim() != 2 or A.shape[0] != 6 or (A.shape[1] > 1 and A.stride(1) != 1):
+        raise ValueError("SoA input must have shape (6, n) with unit column stride")
+    n = A.shape[1]
+    if n == 0:
+        return 0, 0
+    ld = A.stride(0)
+    if ld < n:
+        raise ValueError(f"SoA input planes overlap: row stride {ld} is below n = {n} "
+                         "(a broadcast or overlapping view); pass a (6, n) tensor whose "
+                         "rows are disjoint, e.g. A.contiguous()")
+    return n, ld
+
+
 def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
           flags: int = 0, info: bool = False, out=None, stream=None,
           refine: bool = True):
@@ -103,10 +123,7 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
         raise ValueError("A must be a GPU tensor (the solver has no CPU path)")
     dt = _dtype_code(A, refine)
     if layout == "soa":
-        if A.dim() != 2 or A.shape[0] != 6 or A.stride(1) != 1:
-            raise ValueError("SoA input must have shape (6, n) with unit column stride")
-        n = A.shape[1]
-        ld = A.stride(0) if n > 0 else 0
+        n, ld = _soa_geometry(A)
         if out is None:
             lam_buf = torch.empty((3, max(ld, 1)), dtype=A.dtype, device=A.device)
             V_buf = (torch.empty((9, max(ld, 1)), dtype=A.dtype, device=A.device)

@@ -22,6 +22,7 @@ FLAG_NO_H_GUARD = 2
 FLAG_NEWTON = 4
 FLAG_PAPER_BG = 8
 FLAG_REFINE_CONVERGE = 16
+FLAG_NO_SCALE = 32
 
 E = {
     0: "OK", -1: "E_N", -2: "E_NULL", -3: "E_DTYPE", -4: "E_LAYOUT",

@@ -22,10 +22,11 @@ hipError_t launch_batched(int64_t n, const void* A, int64_t ld, int layout,
 // ceil(n / kBlock)) of the tick's tile space, so no workgroup spans two
 // segments.
 struct Segment {
-  const void* A;
-  void* lambda;
-  void* V;        // NULL: eigenvalues only
+  const void* A;  // 6 planes of n, plane stride lda
+  void* lambda;   // 3 planes of n, plane stride n
+  void* V;        // 9 planes of n, plane stride n; NULL: eigenvalues only
   int64_t n;
+  int64_t lda;    // >= n
   int64_t tile_begin;
   int32_t dtype;
   uint32_t flags;

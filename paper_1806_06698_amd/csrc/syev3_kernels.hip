@@ -319,10 +319,10 @@ __device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t i) 
   const T* A = (const T*)s.A;
   T* lam = (T*)s.lambda;
   T* V = (T*)s.V;
-  const int64_t ld = s.n;
+  const int64_t lda = s.lda, ld = s.n;
   double a[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream(A + k * ld + i);
+  for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream(A + k * lda + i);
   double l[3], v[9];
   if (V) {
     solve3<true, std::is_same<T, float>::value>(a, s.flags, l, v);

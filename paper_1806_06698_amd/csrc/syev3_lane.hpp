@@ -49,6 +49,7 @@ constexpr uint32_t kFlagNoHGuard = 2u;
 constexpr uint32_t kFlagNewton = 4u;
 constexpr uint32_t kFlagPaperBG = 8u;
 constexpr uint32_t kFlagRefineConverge = 16u;
+constexpr uint32_t kFlagNoScale = 32u;
 // internal: FP32 zero finder without the FP64 Newton step and without the
 // re-orthogonalisation (an ablation of the refinement); never set by callers
 constexpr uint32_t kFlagUnrefined = 1u << 31;
@@ -577,7 +578,8 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
                                                  __builtin_fmax(dabs(a13), dabs(a22))),
                                   __builtin_fmax(dabs(a23), dabs(a33)));
   // scale by 2^-e so that max |a_ij| is in [1/2, 1); m == 0 keeps e = 0
-  const int e = __builtin_amdgcn_frexp_exp(m);
+  // (kFlagNoScale, a uniform flag: e = 0, the unscaled matrix)
+  const int e = __builtin_amdgcn_frexp_exp(m) & ((flags & kFlagNoScale) ? 0 : ~0);
   a11 = __builtin_amdgcn_ldexp(a11, -e);
   a12 = __builtin_amdgcn_ldexp(a12, -e);
   a13 = __builtin_amdgcn_ldexp(a13, -e);

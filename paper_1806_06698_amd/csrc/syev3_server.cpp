@@ -60,10 +60,16 @@ struct Request {
   int dtype = 0;
   bool vecs = true;
   size_t off = 0, bytes = 0;
-  void* A = nullptr;
+  const void* A = nullptr;
+  int64_t lda = 0;      // plane stride of A (n, or the caller's for a view)
+  bool view = false;    // A is the caller's memory (syev3_server_acquire_view)
   void* lam = nullptr;
   void* V = nullptr;
+  // What the tick waits for before reading A: the server's own event (own)
+  // recorded behind the caller's, or an event the load generator keeps
+  // alive itself.  NULL: A is complete already.
   hipEvent_t ready = nullptr;
+  hipEvent_t own = nullptr;  // created on this slot's first submit with an event
   // host staging (NULL when the request's data lives on the device)
   const void* h_A = nullptr;
   void* h_lam = nullptr;
@@ -98,6 +104,10 @@ struct syev3_server {
   syev3_server_opts o{};
   int device = 0;
   char* pool = nullptr;
+  // Submissions with a ready event: the server waits for the caller's event
+  // here at submit and records its own per-request event behind it, so the
+  // caller may destroy or re-record its event as soon as submit returns.
+  hipStream_t ingress = nullptr;
   syev3::PoolAllocator* alloc = nullptr;
   std::vector<Request> req;
   std::vector<int> free_slots;
@@ -170,6 +180,7 @@ int syev3_server::launch_tick(int slot) {
     sg.lambda = r.lam;
     sg.V = r.vecs ? r.V : nullptr;
     sg.n = r.n;
+    sg.lda = r.lda;
     sg.tile_begin = tiles;
     sg.dtype = r.dtype;
     sg.flags = 0;
@@ -184,7 +195,8 @@ int syev3_server::launch_tick(int slot) {
     last_ready = r.ready;
     if (r.h_A && e == hipSuccess) {
       const size_t es = r.dtype == SYEV3_F64 ? 8 : 4;
-      e = hipMemcpyAsync(r.A, r.h_A, 6 * (size_t)r.n * es, hipMemcpyHostToDevice, tk.stream);
+      e = hipMemcpyAsync(const_cast<void*>(r.A), r.h_A, 6 * (size_t)r.n * es,
+                         hipMemcpyHostToDevice, tk.stream);
     }
     if (r.h_lam) staged_out = true;
   }
@@ -300,6 +312,10 @@ int syev3_server::init(const syev3_server_opts& opts) {
     return SYEV3_E_BUDGET;
   }
   alloc = new syev3::PoolAllocator(o.hbm_budget_bytes);
+  if (hipStreamCreateWithFlags(&ingress, hipStreamNonBlocking) != hipSuccess) {
+    ingress = nullptr;
+    return SYEV3_E_HIP;
+  }
   req.resize(o.max_requests);
   free_slots.reserve(o.max_requests);
   for (int k = o.max_requests - 1; k >= 0; --k) free_slots.push_back(k);
@@ -333,6 +349,69 @@ int syev3_server::init(const syev3_server_opts& opts) {
   thr = std::thread([this] { scheduler(); });
   return SYEV3_OK;
 }
+
+namespace {
+
+// Admission.  A == NULL: the request's input, eigenvalues and vectors all
+// take pool memory (A has plane stride n).  A != NULL: the input is the
+// caller's device memory with plane stride lda (a view; nothing copied) and
+// only the outputs take pool memory.
+int64_t admit(syev3_server* s, int64_t n, int dtype, int want_vectors, const void* A,
+              int64_t lda, syev3_request_buffers* bufs) {
+  if (!s || !bufs) return SYEV3_E_NULL;
+  if (n < 1 || n > ((int64_t)1 << 40)) return SYEV3_E_N;
+  if (dtype != SYEV3_F64 && dtype != SYEV3_F32_REFINE) return SYEV3_E_DTYPE;
+  if (A && (lda < n || lda > ((int64_t)1 << 40))) return SYEV3_E_LAYOUT;
+  const bool vecs = want_vectors != 0;
+  const size_t es = dtype == SYEV3_F64 ? 8 : 4;
+  const size_t in_bytes = A ? 0 : align_up(6 * (size_t)n * es);
+  const size_t bytes = in_bytes + align_up(3 * (size_t)n * es) +
+                       (vecs ? align_up(9 * (size_t)n * es) : 0);
+  if (bytes > s->o.hbm_budget_bytes) return SYEV3_E_BUDGET;
+  std::lock_guard<std::mutex> lk(s->mu);
+  size_t off = 0;
+  bool got = false;
+  if (!s->free_slots.empty()) {
+    try {
+      got = s->alloc->alloc(bytes, &off);
+    } catch (const std::bad_alloc&) {
+      return SYEV3_E_NOMEM;  // the allocator is unchanged (strong guarantee)
+    }
+  }
+  if (!got) {
+    s->st.acquire_rejections++;
+    return SYEV3_E_AGAIN;
+  }
+  const int slot = s->free_slots.back();
+  s->free_slots.pop_back();
+  Request& r = s->req[slot];
+  r.state = kAdmitted;
+  r.n = n;
+  r.dtype = dtype;
+  r.vecs = vecs;
+  r.off = off;
+  r.bytes = bytes;
+  r.view = A != nullptr;
+  r.A = A ? A : (const void*)(s->pool + off);
+  r.lda = A ? lda : n;
+  r.lam = s->pool + off + in_bytes;
+  r.V = vecs ? s->pool + off + in_bytes + align_up(3 * (size_t)n * es) : nullptr;
+  r.ready = nullptr;
+  r.failed = false;
+  r.h_A = nullptr;
+  r.h_lam = nullptr;
+  r.h_V = nullptr;
+  s->st.pool_bytes_in_use = s->alloc->in_use();
+  s->st.pool_bytes_peak = std::max<uint64_t>(s->st.pool_bytes_peak, s->alloc->in_use());
+  bufs->A = const_cast<void*>(r.A);
+  bufs->lambda = r.lam;
+  bufs->V = r.V;
+  bufs->n = n;
+  bufs->dtype = dtype;
+  return make_id(slot, r.gen);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -395,6 +474,12 @@ int syev3_server_destroy(syev3_server* s) {
     if (tk.done) (void)hipEventDestroy(tk.done);
     if (tk.stream) (void)hipStreamDestroy(tk.stream);
   }
+  if (s->ingress) {
+    (void)hipStreamSynchronize(s->ingress);
+    (void)hipStreamDestroy(s->ingress);
+  }
+  for (auto& r : s->req)
+    if (r.own) (void)hipEventDestroy(r.own);
   if (s->pool) (void)hipFree(s->pool);
   delete s->alloc;
   delete s;
@@ -403,45 +488,13 @@ int syev3_server_destroy(syev3_server* s) {
 
 int64_t syev3_server_acquire(syev3_server* s, int64_t n, int dtype, int want_vectors,
                              syev3_request_buffers* bufs) {
-  if (!s || !bufs) return SYEV3_E_NULL;
-  if (n < 1 || n > ((int64_t)1 << 40)) return SYEV3_E_N;
-  if (dtype != SYEV3_F64 && dtype != SYEV3_F32_REFINE) return SYEV3_E_DTYPE;
-  const bool vecs = want_vectors != 0;
-  const size_t bytes = request_bytes(n, dtype, vecs);
-  if (bytes > s->o.hbm_budget_bytes) return SYEV3_E_BUDGET;
-  std::lock_guard<std::mutex> lk(s->mu);
-  size_t off = 0;
-  if (s->free_slots.empty() || !s->alloc->alloc(bytes, &off)) {
-    s->st.acquire_rejections++;
-    return SYEV3_E_AGAIN;
-  }
-  const int slot = s->free_slots.back();
-  s->free_slots.pop_back();
-  Request& r = s->req[slot];
-  const size_t es = dtype == SYEV3_F64 ? 8 : 4;
-  r.state = kAdmitted;
-  r.n = n;
-  r.dtype = dtype;
-  r.vecs = vecs;
-  r.off = off;
-  r.bytes = bytes;
-  r.A = s->pool + off;
-  r.lam = s->pool + off + align_up(6 * (size_t)n * es);
-  r.V = vecs ? s->pool + off + align_up(6 * (size_t)n * es) + align_up(3 * (size_t)n * es)
-             : nullptr;
-  r.ready = nullptr;
-  r.failed = false;
-  r.h_A = nullptr;
-  r.h_lam = nullptr;
-  r.h_V = nullptr;
-  s->st.pool_bytes_in_use = s->alloc->in_use();
-  s->st.pool_bytes_peak = std::max<uint64_t>(s->st.pool_bytes_peak, s->alloc->in_use());
-  bufs->A = r.A;
-  bufs->lambda = r.lam;
-  bufs->V = r.V;
-  bufs->n = n;
-  bufs->dtype = dtype;
-  return make_id(slot, r.gen);
+  return admit(s, n, dtype, want_vectors, nullptr, 0, bufs);
+}
+
+int64_t syev3_server_acquire_view(syev3_server* s, int64_t n, int dtype, int want_vectors,
+                                  const void* A, int64_t lda, syev3_request_buffers* bufs) {
+  if (!A) return SYEV3_E_NULL;
+  return admit(s, n, dtype, want_vectors, A, lda, bufs);
 }
 
 int syev3_server_submit(syev3_server* s, int64_t id, hipEvent_t ready) {
@@ -451,13 +504,27 @@ int syev3_server_submit(syev3_server* s, int64_t id, hipEvent_t ready) {
     int slot;
     Request* r = lookup(s, id, &slot);
     if (!r || r->state != kAdmitted) return SYEV3_E_STATE;
+    hipEvent_t own = nullptr;
+    if (ready) {
+      // Wait for the caller's event now, on the server's ingress stream,
+      // and mark that point with the request's own event: the tick waits on
+      // that one, so the caller's event is free for reuse once this returns.
+      if (!r->own && hipEventCreateWithFlags(&r->own, hipEventDisableTiming) != hipSuccess) {
+        r->own = nullptr;
+        return SYEV3_E_HIP;  // still admitted
+      }
+      if (hipStreamWaitEvent(s->ingress, ready, 0) != hipSuccess ||
+          hipEventRecord(r->own, s->ingress) != hipSuccess)
+        return SYEV3_E_HIP;  // still admitted
+      own = r->own;
+    }
     try {
       s->queue.push_back(slot);
     } catch (const std::bad_alloc&) {
       return SYEV3_E_NOMEM;  // still admitted
     }
     r->state = kQueued;
-    r->ready = ready;
+    r->ready = own;
     r->t_submit = Clock::now();
     s->note_queue();
     s->st.submitted++;
@@ -474,7 +541,8 @@ int syev3_server_submit_host(syev3_server* s, int64_t id, const void* host_A,
     std::lock_guard<std::mutex> lk(s->mu);
     int slot;
     Request* r = lookup(s, id, &slot);
-    if (!r || r->state != kAdmitted) return SYEV3_E_STATE;
+    // a view's input is the caller's device memory: there is nothing to stage
+    if (!r || r->state != kAdmitted || r->view) return SYEV3_E_STATE;
     try {
       s->queue.push_back(slot);
     } catch (const std::bad_alloc&) {
@@ -534,7 +602,11 @@ int syev3_server_release(syev3_server* s, int64_t id) {
   int slot;
   Request* r = lookup(s, id, &slot);
   if (!r || (r->state != kDone && r->state != kAdmitted)) return SYEV3_E_STATE;
-  s->alloc->release(r->off, r->bytes);
+  try {
+    s->alloc->release(r->off, r->bytes);
+  } catch (const std::bad_alloc&) {
+    return SYEV3_E_NOMEM;  // nothing changed: the request is still held
+  }
   s->st.pool_bytes_in_use = s->alloc->in_use();
   r->state = kFree;
   s->cv_done.notify_all();  // a waiter on this id ends with E_STATE
@@ -564,7 +636,8 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
       !(o->duration_s <= 1e6) || (!closed && !(o->qps * o->duration_s <= 1e8)) ||
       o->src_n < 1 || !o->src_f64 || !o->src_f32 || !(o->max_log2_n >= 0) ||
       !(o->max_log2_n <= 40) ||
-      (o->host_staged && (!o->sink || std::exp2(o->max_log2_n) > (double)o->src_n)))
+      (o->host_staged && (!o->sink || std::exp2(o->max_log2_n) > (double)o->src_n)) ||
+      (o->host_staged && o->input_views))
     return SYEV3_E_N;
   std::memset(out, 0, sizeof(*out));
   // the ready-event ring and the completion list are made before anything
@@ -599,6 +672,7 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
   struct Arrival {
     double t;
     int64_t n;
+    int64_t off;  // the request's window of the device source pool
     int dtype;
   };
   struct Live {
@@ -632,6 +706,8 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
     const double nd = std::floor(std::exp2(U(rng) * o->max_log2_n));
     a.n = std::max<int64_t>(1, (int64_t)std::min((double)o->src_n, nd));
     a.dtype = U(rng) < o->frac_f32 ? SYEV3_F32_REFINE : SYEV3_F64;
+    a.off = std::min<int64_t>(o->src_n - a.n,
+                              (int64_t)(U(rng) * (double)(o->src_n - a.n + 1)));
     return a;
   };
   for (;;) {
@@ -652,15 +728,20 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
     // the copies, and the group is submitted with that event as its ready
     // point: the tick waits for the copies on the device while the host goes
     // on with the next group, so input copies overlap the solves of ticks
-    // already launched.
+    // already launched.  With input views nothing is copied: a request reads
+    // its window of the source pool, which is complete before the run, and
+    // is submitted with no ready event.
     batch.clear();
     auto flush = [&]() {
       if (batch.empty() || rc != SYEV3_OK) return;
-      hipEvent_t ev = ring[ring_next];
-      ring_next = (ring_next + 1) % ring.size();
-      if (hipEventRecord(ev, prod) != hipSuccess) {
-        rc = SYEV3_E_HIP;
-        return;
+      hipEvent_t ev = nullptr;
+      if (!o->input_views) {
+        ev = ring[ring_next];
+        ring_next = (ring_next + 1) % ring.size();
+        if (hipEventRecord(ev, prod) != hipSuccess) {
+          rc = SYEV3_E_HIP;
+          return;
+        }
       }
       {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -683,7 +764,13 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
     while (!waiting.empty()) {
       const Arrival a = waiting.front();
       syev3_request_buffers b;
-      const int64_t id = syev3_server_acquire(s, a.n, a.dtype, o->want_vectors, &b);
+      const size_t es = a.dtype == SYEV3_F64 ? 8 : 4;
+      const char* src = (const char*)(a.dtype == SYEV3_F64 ? o->src_f64 : o->src_f32);
+      const int64_t id =
+          o->input_views
+              ? syev3_server_acquire_view(s, a.n, a.dtype, o->want_vectors,
+                                          src + (size_t)a.off * es, o->src_n, &b)
+              : syev3_server_acquire(s, a.n, a.dtype, o->want_vectors, &b);
       if (id == SYEV3_E_AGAIN) break;
       if (id < 0) { rc = (int)id; break; }
       waiting.pop_front();
@@ -696,8 +783,6 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
       }
       admit_wait_sum += seconds_since(t0, Clock::now()) - a.t;
       admitted++;
-      const size_t es = a.dtype == SYEV3_F64 ? 8 : 4;
-      const char* src = (const char*)(a.dtype == SYEV3_F64 ? o->src_f64 : o->src_f32);
       if (o->host_staged) {
         // the request's input is the first 6 n values of the host source;
         // every request's results land in the same host sink
@@ -706,10 +791,10 @@ int syev3_server_loadgen(syev3_server* s, const syev3_loadgen_opts* o,
                                       o->want_vectors ? sink + 3 * (size_t)a.n * es : nullptr);
         if (rc != SYEV3_OK) break;
       } else {
-        // a random window of the source pool
-        const int64_t off = std::min<int64_t>(
-            o->src_n - a.n, (int64_t)(U(rng) * (double)(o->src_n - a.n + 1)));
-        if (hipMemcpy2DAsync(b.A, (size_t)a.n * es, src + (size_t)off * es,
+        // a random window of the source pool: read in place (a view), or
+        // copied into the request's own input buffer
+        if (!o->input_views &&
+            hipMemcpy2DAsync(b.A, (size_t)a.n * es, src + (size_t)a.off * es,
                              (size_t)o->src_n * es, (size_t)a.n * es, 6,
                              hipMemcpyDeviceToDevice, prod) != hipSuccess) {
           rc = SYEV3_E_HIP;

@@ -18,7 +18,7 @@ class LoadgenOpts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("src_f64", ctypes.c_void_p),
                 ("src_f32", ctypes.c_void_p), ("src_n", ctypes.c_int64),
                 ("want_vectors", ctypes.c_int32), ("host_staged", ctypes.c_int32),
-                ("sink", ctypes.c_void_p)]
+                ("sink", ctypes.c_void_p), ("input_views", ctypes.c_int32)]
 
 
 class LoadgenResult(ctypes.Structure):
@@ -43,6 +43,10 @@ def _bind(L):
     L.syev3_server_submit_host.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p]
     L.syev3_server_submit_host.restype = ctypes.c_int
+    L.syev3_server_acquire_view.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+                                            ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.POINTER(RequestBuffers)]
+    L.syev3_server_acquire_view.restype = ctypes.c_int64
     L._serve_bound = True
     return L
 
@@ -92,19 +96,20 @@ def check_loadgen_sources(src_f64, src_f32, max_log2_n, sink):
 
 
 class Request:
-    """An admitted request: device tensors over the server's pool."""
+    """An admitted request: device tensors over the server's pool (A is the
+    caller's own tensor for a request admitted as a view)."""
 
-    def __init__(self, server, rid, bufs: RequestBuffers, dtype):
+    def __init__(self, server, rid, bufs: RequestBuffers, dtype, A=None):
         self.server, self.id, self.n = server, rid, bufs.n
         self.dtype = bufs.dtype
         tdt = torch.float64 if bufs.dtype == _lib.F64 else torch.float32
         es = 8 if tdt == torch.float64 else 4
         dev = server.device
-        self.A = _tensor_at(bufs.A, (6, bufs.n), tdt, es, dev)
+        # a view's input: the caller's tensor, held until release
+        self.A = A if A is not None else _tensor_at(bufs.A, (6, bufs.n), tdt, es, dev)
         self.lam = _tensor_at(bufs.lam, (3, bufs.n), tdt, es, dev)
         self.V = _tensor_at(bufs.V, (9, bufs.n), tdt, es, dev) if bufs.V else None
-        self.ready_event = None  # held from submit to release
-        self.host_buffers = None  # likewise, for host-staged requests
+        self.host_buffers = None  # held from a host-staged submit to release
 
 
 def _tensor_at(ptr, shape, dtype, esize, dev):
@@ -169,14 +174,37 @@ class Server:
         _lib.check(rid, "syev3_server_acquire")
         return Request(self, rid, b, dtype)
 
+    def acquire_view(self, A: torch.Tensor, vectors=True):
+        """Admit a request whose input is the caller's tensor A, (6, n) with
+        unit column stride and row stride >= n, on the server's device,
+        float64 (FP64) or float32 (FP32 storage + refinement).  A is read in
+        place by the tick (not copied); only the outputs take pool memory.
+        The request holds A until release.  None when the pool or the slots
+        are full now."""
+        from . import _soa_geometry
+        if not A.is_cuda or A.device != torch.device(f"cuda:{self.device}"):
+            raise ValueError(f"A must be on cuda:{self.device}, the server's device")
+        n, lda = _soa_geometry(A)
+        if n == 0:
+            raise ValueError("a request holds at least one matrix")
+        dtype = {torch.float64: _lib.F64, torch.float32: _lib.F32_REFINE}.get(A.dtype)
+        if dtype is None:
+            raise TypeError(f"A must be float64 or float32, got {A.dtype}")
+        b = RequestBuffers()
+        rid = self.L.syev3_server_acquire_view(self.h, n, dtype, 1 if vectors else 0,
+                                               A.data_ptr(), lda, ctypes.byref(b))
+        if rid == _lib.E_AGAIN:
+            return None
+        _lib.check(rid, "syev3_server_acquire_view")
+        return Request(self, rid, b, dtype, A=A)
+
     def submit(self, req: Request, ready_event=None):
         """Queue req; its tick waits on the device for ready_event (a
-        torch.cuda.Event recorded after req.A was written).  The server waits
-        on the event only when it launches the tick, so the request keeps a
-        reference to it until release: the caller may drop its own."""
+        torch.cuda.Event recorded after req.A was written).  The server takes
+        its own mark of the event during this call, so the event may be
+        dropped or recorded again as soon as submit returns."""
         ev = ctypes.c_void_p(ready_event.cuda_event if ready_event is not None else 0)
         _lib.check(self.L.syev3_server_submit(self.h, req.id, ev), "syev3_server_submit")
-        req.ready_event = ready_event
 
     def submit_host(self, req: Request, host_A, host_lam, host_V=None):
         """Host-staged submission: host_A (6, n), host_lam (3, n), host_V
@@ -203,7 +231,6 @@ class Server:
 
     def release(self, req):
         _lib.check(self.L.syev3_server_release(self.h, req.id), "syev3_server_release")
-        req.ready_event = None
         req.host_buffers = None
 
     def stats(self) -> dict:
@@ -212,19 +239,24 @@ class Server:
         return {f: getattr(s, f) for f, _ in s._fields_}
 
     def loadgen(self, src_f64, src_f32, qps, duration_s, max_log2_n=20.0,
-                frac_f32=0.5, seed=0, vectors=True, concurrency=0, sink=None) -> dict:
+                frac_f32=0.5, seed=0, vectors=True, concurrency=0, sink=None,
+                input_views=False) -> dict:
         """qps > 0: open-loop Poisson arrivals; qps == 0: closed loop with
         `concurrency` requests in flight.  Sources on the device: inputs are
-        copied on the device.  Sources in (pinned) host memory together with a
-        host `sink`: host-staged requests."""
+        copied on the device, or with input_views read in place (each request
+        a view of its window of the source).  Sources in (pinned) host memory
+        together with a host `sink`: host-staged requests."""
         check_loadgen_sources(src_f64, src_f32, max_log2_n, sink)
         staged = not src_f64.is_cuda
+        if staged and input_views:
+            raise ValueError("input views need device sources")
         o = LoadgenOpts(qps=qps, closed_concurrency=concurrency,
                         duration_s=duration_s, max_log2_n=max_log2_n,
                         frac_f32=frac_f32, seed=seed, src_f64=src_f64.data_ptr(),
                         src_f32=src_f32.data_ptr(), src_n=src_f64.shape[-1],
                         want_vectors=1 if vectors else 0, host_staged=1 if staged else 0,
-                        sink=sink.data_ptr() if sink is not None else None)
+                        sink=sink.data_ptr() if sink is not None else None,
+                        input_views=1 if input_views else 0)
         r = LoadgenResult()
         _lib.check(self.L.syev3_server_loadgen(self.h, ctypes.byref(o), ctypes.byref(r)),
                    "syev3_server_loadgen")

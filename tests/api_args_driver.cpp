@@ -66,7 +66,7 @@ Span span_of(uint64_t p, int64_t n, int64_t ld, int layout, int planes, int es) 
 bool model_valid(int64_t n, uint64_t A, int64_t ld, int layout, uint64_t lam, uint64_t V,
                  int dtype, uint32_t flags, uint64_t info, bool allow_inplace) {
   if (dtype < 0 || dtype > 2) return false;
-  if (flags & ~31u) return false;
+  if (flags & ~63u) return false;
   if ((flags & 12u) && dtype != 0) return false;  // Newton, paper BG: FP64 only
   if ((flags & 4u) && (flags & 8u)) return false;  // not both
   if ((flags & 16u) && dtype != 1) return false;  // converge: FP32 refined only
@@ -124,7 +124,7 @@ int main(int argc, char** argv) {
     if (far && (ld > ((int64_t)1 << 40) || ld < -((int64_t)1 << 40))) ld = 0;
     const int layout = (int)pick({0, 0, 1, 2, -1, 3});
     const int dtype = (int)pick({0, 0, 1, 2, -1, 3});
-    const uint32_t flags = (uint32_t)pick({0, 0, 0, 1, 2, 4, 7, 8, 12, 15, 16, 17, 19, 31, 32,
+    const uint32_t flags = (uint32_t)pick({0, 0, 0, 1, 2, 4, 7, 8, 12, 15, 16, 17, 19, 31, 32, 33, 63, 64,
                                            0x7fffffff});
     // addresses: separate regions or overlapping ones, 0 for NULL
     const uint64_t base = (uint64_t)1 << 44;
@@ -188,7 +188,7 @@ int main(int argc, char** argv) {
           (uint64_t)g_launch.V != V || g_launch.dtype != dtype)
         fail("launcher got other pointers or sizes", i);
       if (which != 4 && (g_launch.ld != want_ld || g_launch.layout != exp_layout ||
-                         (g_launch.flags & 31u) != exp_flags || (uint64_t)g_launch.info != info))
+                         (g_launch.flags & 63u) != exp_flags || (uint64_t)g_launch.info != info))
         fail("launcher got another layout, stride, flags or info", i);
     }
     if (far) {

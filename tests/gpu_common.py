@@ -76,3 +76,42 @@ def sample_indices(n, k, seed, cat=None):
             w = np.flatnonzero(c == v)
             idx.append(g.choice(w, size=min(len(w), max(1, k // 8)), replace=False))
     return np.unique(np.concatenate(idx))
+
+
+def check_vs_oracle(A, lam, V, f32=False, sample=None, seed=0, label=""):
+    """Results of the GPU path against the CPU oracle on the same input, at
+    the acceptance bars: FP64 16 eps ||A||_F (eigenvalues, residual) and
+    16 eps (orthogonality); FP32 storage (refined) 1 eps32 ||A||_F,
+    3 eps32 ||A||_F and 3 eps32, against the FP64 oracle on the FP32 values
+    widened exactly.  A (6, n) SoA, lam (3, n), V (9, n) or None, on any
+    device and of the input's dtype.  sample: check only that many matrices
+    (drawn at random with `seed`); None: all.  Returns the worst errors in
+    units of the eps of the dtype."""
+    import checks
+    import oracle
+    n = A.shape[1]
+    idx = None
+    if sample is not None and n > sample:
+        idx = torch.from_numpy(np.sort(np.random.default_rng(seed).choice(n, sample,
+                                                                           replace=False)))
+    def take(t):
+        t = t.detach().to("cpu")
+        return t[:, idx] if idx is not None else t
+    A6 = take(A).double().t().contiguous().numpy()
+    l = take(lam).double().t().numpy()
+    lam_o, _ = oracle.solve(A6)
+    unit = EPS32 / EPS64 if f32 else 1.0
+    bar = {"lam": 1.0, "res": 3.0, "orth": 3.0} if f32 else {"lam": 16.0, "res": 16.0,
+                                                               "orth": 16.0}
+    e = checks.eig_error(A6, l, lam_o).max() / unit
+    out = {"lam": e}
+    if V is not None:
+        v = take(V).double().t().numpy().reshape(-1, 3, 3)
+        out["res"] = checks.residual(A6, l, v).max() / unit
+        out["orth"] = checks.orthogonality(v).max() / unit
+    print(f"  {label} n={n} checked {A6.shape[0]} vs oracle: "
+          + ", ".join(f"{k} {x:.2f}" for k, x in out.items())
+          + (" eps32" if f32 else " eps"), flush=True)
+    for k, x in out.items():
+        assert x <= bar[k], f"{label}: {k} error {x:.2f} above {bar[k]}"
+    return out

@@ -88,7 +88,7 @@ def test_bad_arguments_are_rejected(L, no_device):
     assert ex(10, A, 0, 0, LAM, VV, 0, 12, S) == -7            # Newton and paper BG
     assert ex(10, A, 0, 0, LAM, VV, 0, 16, S) == -3            # converge needs F32_REFINE
     assert ex(10, A, 0, 0, LAM, VV, 2, 16, S) == -3
-    assert ex(10, A, 0, 0, LAM, VV, 0, 32, S) == -7            # unknown flag
+    assert ex(10, A, 0, 0, LAM, VV, 0, 128, S) == -7           # unknown flag
     assert ex(10, A, 0, 0, LAM, VV, 3, 0, S) == -3
     # the unrefined FP32 dtype has FP32 spans: lambda 4 bytes past A's end is fine
     assert ex(10, A, 0, 1, ctypes.c_void_p(0x100000 + 4 * 59), NUL, 2, 0, S) == -5

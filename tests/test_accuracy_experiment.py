@@ -30,17 +30,36 @@ def test_oracle_on_the_paper_distributions(oracle_mod, k, dist):
 
 
 @pytest.mark.gpu
-def test_gpu_on_the_paper_distributions():
+def test_gpu_on_the_paper_distributions(oracle_mod):
+    """The experiment on the GPU path: per matrix, orthogonality <= 16 eps
+    and residual <= 16 eps ||T||_F (the acceptance bar, relative as for
+    every other workload), and eigenvalues within 16 eps ||T||_F of the
+    oracle on the same matrices.  The comparison with LAPACK is printed."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    res = accuracy.run(n=20_000, seed=0)
-    for dist in accuracy.DISTS:
+    import paper_1806_06698_amd as s3
+    n, seed = 20_000, 0
+    res = accuracy.run(n=n, seed=seed)
+    for k, dist in enumerate(accuracy.DISTS):
         r = res[dist]
         print(dist, {m: (round(r[m]["ours_median_eps"], 3), round(r[m]["lapack_median_eps"], 3),
                          round(r[m]["lapack_minus_ours"]["ours_better"], 3))
                      for m in ("orthogonality", "residual")}, flush=True)
-        assert r["orthogonality"]["ours_max_eps"] <= 16
-        # residual bar is relative to ||T||_F, which is below 16 for these
-        # entries except chi-square tails: bound the absolute value loosely
-        assert r["residual"]["ours_max_eps"] <= 16 * 40
+        # the same matrices as the run above (seed + k), solved again here
+        A = gen.paper_dist(n, dist, seed=seed + k, device="cpu")
+        lam_d, V_d = s3.syev3(A.cuda())
+        torch.cuda.synchronize()
+        lam = lam_d.t().cpu().numpy()
+        V = V_d.t().cpu().numpy().reshape(-1, 3, 3)
+        A6 = gen.to_aos(A).numpy()
+        orth, resid = accuracy.measures(A6, lam, V)
+        fro = np.linalg.norm(checks.full(A6), axis=(1, 2))
+        lam_o, _ = oracle_mod.solve(A6)
+        e = checks.eig_error(A6, lam, lam_o)
+        print(f"  {dist}: orth max {orth.max() / EPS:.2f} eps, residual max "
+              f"{(resid / fro).max() / EPS:.2f} eps|T|, |dlam| vs oracle max {e.max():.2f} "
+              f"eps|T|", flush=True)
+        assert orth.max() <= 16 * EPS
+        assert (resid / fro).max() <= 16 * EPS
+        assert e.max() <= 16

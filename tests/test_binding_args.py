@@ -28,3 +28,36 @@ def test_out_tensors_are_checked():
     s3._check_out(aos, (n, 3, 3), (9, 3, 1), A, "V")
     with pytest.raises(ValueError):
         s3._check_out(aos.transpose(1, 2), (n, 3, 3), (9, 3, 1), A, "V")
+
+
+def test_soa_input_planes_must_be_disjoint():
+    n = 10
+    ok = torch.zeros(6, n, dtype=torch.float64)
+    assert s3._soa_geometry(ok) == (n, n)
+    assert s3._soa_geometry(torch.zeros(6, 2 * n, dtype=torch.float64)[:, :n]) == (n, 2 * n)
+    assert s3._soa_geometry(torch.zeros(6, 0, dtype=torch.float64)) == (0, 0)
+    assert s3._soa_geometry(torch.zeros(6, 1, dtype=torch.float64)) == (1, 1)
+    # a broadcast row: stride (0, 1), six planes on the same n elements
+    with pytest.raises(ValueError, match="overlap"):
+        s3._soa_geometry(torch.randn(n, dtype=torch.float64).expand(6, n))
+    with pytest.raises(ValueError, match="overlap"):
+        s3._soa_geometry(torch.randn(1, dtype=torch.float64).expand(6, 1))
+    # overlapping planes: a (6, n) window with row stride n // 2
+    buf = torch.zeros(6 * n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="overlap"):
+        s3._soa_geometry(buf.as_strided((6, n), (n // 2, 1)))
+    with pytest.raises(ValueError):
+        s3._soa_geometry(torch.zeros(n, 6, dtype=torch.float64).t())   # column stride 6
+    with pytest.raises(ValueError):
+        s3._soa_geometry(torch.zeros(5, n, dtype=torch.float64))
+
+
+def test_broadcast_out_tensors_are_refused():
+    n = 10
+    A = torch.zeros(6, n, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        s3._check_out(torch.empty(n, dtype=torch.float64).expand(3, n), (3, n), (n, 1), A,
+                      "lam")
+    with pytest.raises(ValueError):
+        s3._check_out(torch.empty(9, dtype=torch.float64).expand(n, 9).t(), (9, n), (n, 1), A,
+                      "V")

@@ -25,7 +25,9 @@ import oracle
 
 EPS = 2.0 ** -52
 HERE = os.path.dirname(os.path.abspath(__file__))
-mpmath.mp.dps = 50
+# working precision of every mpmath evaluation here, set per use (workdps)
+# so that no other test module's precision leaks in or out
+DPS = 50
 
 
 def _cases():
@@ -42,19 +44,20 @@ _NAMES = {"sqrt": mpmath.sqrt, "sin": mpmath.sin, "cos": mpmath.cos, "pi": mpmat
 
 def _value(expr):
     """An expression of the fixture file (numbers, + - * /, sqrt, sin, cos,
-    pi), evaluated in 50-digit arithmetic."""
+    pi), evaluated in the caller's working precision (DPS digits)."""
     return mpmath.mpf(eval(expr, {"__builtins__": {}}, dict(_NAMES)))
 
 
 def _exact(case):
-    lam = [_value(e) for e in case["lambda"]]
-    vecs = []
-    for v in case["vectors"]:
-        if v is None:
-            vecs.append(None)
-            continue
-        u = mpmath.matrix([_value(e) for e in v])
-        vecs.append(u / mpmath.norm(u))
+    with mpmath.workdps(DPS):
+        lam = [_value(e) for e in case["lambda"]]
+        vecs = []
+        for v in case["vectors"]:
+            if v is None:
+                vecs.append(None)
+                continue
+            u = mpmath.matrix([_value(e) for e in v])
+            vecs.append(u / mpmath.norm(u))
     return lam, vecs
 
 
@@ -65,17 +68,18 @@ def _full(A6):
 
 @pytest.mark.parametrize("case", CASES, ids=[c["name"] for c in CASES])
 def test_fixture_is_consistent(case):
-    lam, vecs = _exact(case)
-    A = mpmath.matrix(_full(case["A6"]).tolist())
-    assert lam == sorted(lam)
-    assert abs(sum(lam) - sum(A[i, i] for i in range(3))) < mpmath.mpf(10) ** -40
-    for l, v in zip(lam, vecs):
-        if v is not None:
-            assert mpmath.norm(A * v - l * v) < mpmath.mpf(10) ** -40
-    # eigenvalues against the characteristic polynomial's roots, by mpmath
-    ev = sorted(mpmath.eigsy(A)[0])
-    for a, b in zip(ev, lam):
-        assert abs(a - b) < mpmath.mpf(10) ** -40
+    with mpmath.workdps(DPS):
+        lam, vecs = _exact(case)
+        A = mpmath.matrix(_full(case["A6"]).tolist())
+        assert lam == sorted(lam)
+        assert abs(sum(lam) - sum(A[i, i] for i in range(3))) < mpmath.mpf(10) ** -40
+        for l, v in zip(lam, vecs):
+            if v is not None:
+                assert mpmath.norm(A * v - l * v) < mpmath.mpf(10) ** -40
+        # eigenvalues against the characteristic polynomial's roots, by mpmath
+        ev = sorted(mpmath.eigsy(A)[0])
+        for a, b in zip(ev, lam):
+            assert abs(a - b) < mpmath.mpf(10) ** -40
 
 
 def _check(case, scale, lam, V, tol):

@@ -16,7 +16,7 @@ import checks
 import oracle
 from deflation_cases import DEFLATION_BRANCHES, DEFLATION_CASES
 import paper_1806_06698_amd as s3
-from gpu_common import (EPS64, device_measures, need_gpu, sample_indices,
+from gpu_common import (EPS64, check_vs_oracle, device_measures, need_gpu, sample_indices,
                         soa_to_numpy, solve_soa)
 from paper_1806_06698_amd import gen
 
@@ -80,6 +80,7 @@ def test_many_seeds():
     (s3.FLAG_NO_H_GUARD, oracle.NO_H_GUARD),
     (s3.FLAG_NEWTON, oracle.NEWTON),
     (s3.FLAG_PAPER_BG, 0),                 # the oracle's zero finder is the paper's
+    (s3.FLAG_NO_SCALE, oracle.NO_SCALE),   # no power-of-two scaling (the paper has none)
 ])
 def test_flag_variants(flags, oflags):
     for kind, seed in (("normal", 20), ("spd_fe", 21), ("uniform", 22)):
@@ -466,11 +467,16 @@ def test_full_matrix_layout_and_in_place():
     torch.cuda.synchronize()
     assert torch.equal(lam_a, lam_9) and torch.equal(V_a, V_9)
     assert torch.equal(lam_a, lam_i) and torch.equal(V_a, M)
+    # the full-matrix staging is code of its own: its outputs meet the oracle
+    check_vs_oracle(A, lam_9.t(), V_9.reshape(-1, 9).t(), label="aos9")
+    check_vs_oracle(A, lam_i.t(), M.reshape(-1, 9).t(), label="in place")
     f32 = full.float().cuda()
     lam_f = s3.syev3_inplace(f32)
     lam_fa, V_fa = s3.syev3(gen.to_aos(A).float().cuda(), layout="aos")
     torch.cuda.synchronize()
     assert torch.equal(lam_f, lam_fa) and torch.equal(f32, V_fa)
+    check_vs_oracle(A.float(), lam_f.t(), f32.reshape(-1, 9).t(), f32=True,
+                    label="in place fp32")
 
 
 @pytest.mark.parametrize("layout", [s3.SOA, s3.AOS])

@@ -243,16 +243,17 @@ def test_bg_cubic_convergence(oracle_mod):
     arrow from a 40-digit library eigensolver, and only above the rounding
     floor of the evaluation of f."""
     mpmath = pytest.importorskip("mpmath")
-    mpmath.mp.dps = 40
     arrows = _reduced_arrows(oracle_mod, 1500, 22)
     orders = []
     for b1, b2, ab, gb in arrows:
         x, _, tr = oracle_mod.bg_root(b1, b2, ab, gb, trace_cap=64)
         if len(tr) < 3:
             continue
-        M = mpmath.matrix([[0, 0, b1], [0, -ab, b2], [b1, b2, gb]])
-        root = max(mpmath.eigsy(M, eigvals_only=True))
-        e = [float(abs((mpmath.mpf(float(t)) - root) / root)) for t in tr]
+        # 40 digits for this test only (workdps restores the caller's)
+        with mpmath.workdps(40):
+            M = mpmath.matrix([[0, 0, b1], [0, -ab, b2], [b1, b2, gb]])
+            root = max(mpmath.eigsy(M, eigvals_only=True))
+            e = [float(abs((mpmath.mpf(float(t)) - root) / root)) for t in tr]
         floor = 1e3 * EPS * max(1.0, _f_noise(b1, b2, ab, gb, x) / x)
         for j in range(len(e) - 2):
             if e[j] < 0.5 and e[j + 2] > floor:

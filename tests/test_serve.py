@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import paper_1806_06698_amd as s3
-from gpu_common import need_gpu
+from gpu_common import check_vs_oracle, need_gpu
 from paper_1806_06698_amd import gen, serve
 
 pytestmark = pytest.mark.gpu
@@ -48,6 +48,14 @@ def _check_bitwise(req):
         assert torch.equal(V, req.V), f"V differs for n={req.n}"
 
 
+def _check_oracle(req, sample=20_000, label="served"):
+    """The served results themselves against the CPU oracle (the segment
+    kernel is code of its own, so equality with the batched kernel alone
+    would not show it right)."""
+    check_vs_oracle(req.A, req.lam, req.V, f32=req.dtype == s3.F32_REFINE,
+                    sample=sample, seed=req.n, label=f"{label} dtype={req.dtype}")
+
+
 @pytest.mark.parametrize("use_graphs", [True, False])
 def test_each_result_same_alone_and_in_the_mix(source, use_graphs):
     A64, A32 = source
@@ -70,6 +78,7 @@ def test_each_result_same_alone_and_in_the_mix(source, use_graphs):
             assert lat >= 0.0
         for r in reqs:
             _check_bitwise(r)
+            _check_oracle(r)
             srv.release(r)
         st = srv.stats()
         assert st["completed"] == len(sizes)
@@ -169,6 +178,8 @@ def test_host_staged_requests_match_the_device_path(source):
             lam, V = s3.syev3(src)
             torch.cuda.synchronize()
             assert torch.equal(lam.cpu(), hl) and torch.equal(V.cpu(), hV)
+            check_vs_oracle(src, hl, hV, f32=r.dtype == s3.F32_REFINE, sample=20_000,
+                            seed=r.n, label="host-staged")
             srv.release(r)
 
 
@@ -277,3 +288,90 @@ def test_one_segment_per_tick(source):
         st = srv.stats()
         assert st["ticks"] == 12 and st["segments_per_tick_peak"] == 1
         assert st["inflight_ticks_peak"] == 1
+
+
+def test_caller_may_drop_its_ready_event_right_after_submit(source):
+    """The server waits for the caller's event during submit and keeps a
+    mark of its own, so a caller that destroys its event (or records it
+    again) as soon as submit returns still gets its input honoured: every
+    result equals a separate solve of the same input, bitwise."""
+    import gc
+    A64, A32 = source
+    rng = np.random.default_rng(11)
+    with serve.Server(hbm_budget_bytes=1 << 30, max_inflight_ticks=2) as srv:
+        reqs = []
+        reuse = torch.cuda.Event()
+        for k in range(24):
+            n = int(rng.integers(1, 60_000))
+            dt = s3.F64 if k % 2 == 0 else s3.F32_REFINE
+            r = srv.acquire(n, dt)
+            off = int(rng.integers(0, (1 << 21) - n))
+            r.A.copy_((A64 if dt == s3.F64 else A32)[:, off:off + n])
+            if k % 3 == 0:
+                ev = torch.cuda.Event()        # dropped right after submit
+                ev.record()
+                srv.submit(r, ev)
+                del ev
+                gc.collect()
+            else:
+                reuse.record()                 # one event recorded again for the next
+                srv.submit(r, reuse)
+            reqs.append(r)
+        for r in reqs:
+            srv.wait(r, timeout_s=60.0)
+            _check_bitwise(r)
+            srv.release(r)
+        assert srv.stats()["completed"] == 24
+
+
+def test_requests_admitted_as_views_of_the_callers_input(source):
+    """A request admitted as a view reads its input in place from the
+    caller's tensor, with the caller's plane stride (a window of a larger
+    pool), and only its outputs take pool memory.  Its results equal a
+    separate solve bitwise and meet the oracle's bars."""
+    A64, A32 = source
+    ld = A64.shape[1]
+    with serve.Server(hbm_budget_bytes=256 << 20, max_inflight_ticks=2) as srv:
+        reqs = []
+        for k, (n, off) in enumerate([(1, 5), (255, 1000), (70_001, 3), (300_000, 1_500_000)]):
+            src = A64 if k % 2 == 0 else A32
+            view = src[:, off:off + n]
+            assert view.stride(0) == ld
+            r = srv.acquire_view(view, vectors=k != 2)
+            assert r is not None and r.A.data_ptr() == view.data_ptr()
+            srv.submit(r)
+            reqs.append(r)
+        es = {s3.F64: 8, s3.F32_REFINE: 4}
+        used = srv.stats()["pool_bytes_in_use"]
+        want = sum(-(-3 * r.n * es[r.dtype] // 256) * 256
+                   + (-(-9 * r.n * es[r.dtype] // 256) * 256 if r.V is not None else 0)
+                   for r in reqs)
+        assert used == want, (used, want)      # outputs only
+        for r in reqs:
+            srv.wait(r, timeout_s=60.0)
+            lam, V = s3.syev3(r.A.contiguous(), vectors=r.V is not None)
+            torch.cuda.synchronize()
+            assert torch.equal(lam, r.lam) and (V is None or torch.equal(V, r.V))
+            _check_oracle(r, label="view")
+            srv.release(r)
+        # a view has no input of its own to stage from the host
+        r = srv.acquire_view(A64[:, :100])
+        with pytest.raises(s3.Syev3Error) as ei:
+            srv.submit_host(r, A64[:, :100].cpu().contiguous(),
+                            torch.empty(3, 100, dtype=torch.float64))
+        assert ei.value.code == -10
+        srv.submit(r)
+        srv.wait(r, timeout_s=30.0)
+        srv.release(r)
+        with pytest.raises(ValueError):
+            srv.acquire_view(A64[:, :10].t().contiguous().t())  # column stride != 1
+        assert srv.stats()["pool_bytes_in_use"] == 0
+
+
+def test_loadgen_with_input_views(source):
+    A64, A32 = source
+    with serve.Server(hbm_budget_bytes=2 << 30) as srv:
+        res = srv.loadgen(A64, A32, qps=0.0, concurrency=32, duration_s=0.5, max_log2_n=16,
+                          seed=5, input_views=True)
+    print(res, flush=True)
+    assert res["requests"] > 32 and 0 < res["lat_p50_s"] <= res["lat_p99_s"]
