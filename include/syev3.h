@@ -151,6 +151,29 @@ int batched_syev3_ex(int64_t n, const void* A, int64_t ld, int layout,
                      hipStream_t stream);
 
 /*
+ * batched_syev3_strided -- structure-of-arrays with a plane stride of its own
+ * for each array: entry k of matrix i is A[k*lda + i], eigenvalue j is
+ * lambda[j*ldl + i], row r of eigenvector c is V[(3*r + c)*ldv + i].  Each
+ * stride is >= n (0 means n).  The arithmetic is that of batched_syev3_ex,
+ * so the results are bitwise the same for any strides.
+ *
+ * Why separate strides: the 18 planes of an SoA solve are streamed together,
+ * each wavefront touching all of them at the same element offset.  When the
+ * plane stride is a multiple of 1 GiB (n = 2^28 FP64 matrices: planes
+ * exactly 2 GiB apart), the planes' streams can fall on the same HBM
+ * channels at once, depending on where the allocations land; on an MI355X
+ * such a 2^28-matrix FP64 solve took 8.3 ms with every stride n and 6.6 ms
+ * with the strides 32.5 KiB longer.  A caller that cannot choose the layout
+ * of its input can still give the outputs a stride of their own (the Python
+ * binding does for strides within 32.5 KiB of a multiple of 1 GiB).
+ * Arrays whose plane ranges interleave are refused (SYEV3_E_ALIAS) even
+ * when their planes do not overlap.  Errors as batched_syev3_ex.
+ */
+int batched_syev3_strided(int64_t n, const void* A, int64_t lda, void* lambda,
+                          int64_t ldl, void* V, int64_t ldv, int dtype,
+                          uint32_t flags, hipStream_t stream);
+
+/*
  * batched_syev3_inplace -- for callers that keep full 3x3 matrices (one per
  * finite element, say): A is n x 9 row-major (SYEV3_AOS9) and is overwritten
  * by the eigenvectors (column c of each 3x3 is eigenvector c); lambda is n x 3.

@@ -22,6 +22,7 @@ from ._lib import (AOS, AOS9, F32, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD
                    Syev3Error)
 
 __all__ = ["syev3", "syev3_inplace", "batched_syev3", "batched_syev3_ex", "batched_syev3_info",
+           "batched_syev3_strided", "out_stride",
            "F64", "F32_REFINE", "F32", "SOA", "AOS", "AOS9", "FLAG_SIMPLIFIED_DEFLATION",
            "FLAG_NO_H_GUARD", "FLAG_NEWTON", "FLAG_PAPER_BG", "FLAG_REFINE_CONVERGE", "FLAG_NO_SCALE",
            "Syev3Error",
@@ -61,6 +62,38 @@ def batched_syev3_info(n, A_ptr, ld, layout, lam_ptr, V_ptr, dtype, flags,
                                          dtype, flags, info_ptr, stream_handle)
 
 
+def batched_syev3_strided(n, A_ptr, lda, lam_ptr, ldl, V_ptr, ldv, dtype, flags,
+                          stream_handle) -> int:
+    return _lib.lib().batched_syev3_strided(n, A_ptr, lda, lam_ptr, ldl, V_ptr, ldv, dtype,
+                                            flags, stream_handle)
+
+
+# Plane stride of the outputs the binding allocates for SoA solves.  The 12
+# output planes and the 6 input planes are streamed together, each wavefront
+# at the same element offset in every plane.  Planes a multiple of 1 GiB
+# apart (2^27 and 2^28 FP64 matrices) can then meet on the same HBM
+# channels: on an MI355X a 2^28-matrix FP64 solve took 8.3 ms with every
+# stride n and 6.6 ms with the strides offset by 32.5 KiB, depending on
+# where the allocations landed (other runs of the plain layout took 6.5 ms).
+# At 2^26 matrices (planes 512 MiB apart) the same offset made the solve 4%
+# slower, so it is applied only to strides within 32.5 KiB of a multiple of
+# 1 GiB: such a stride is lengthened to 32.5 KiB past the multiple.
+_GIB = 1 << 30
+_STAGGER_BYTES = 33280
+
+
+def out_stride(n: int, esize: int) -> int:
+    """Plane stride (elements) of the SoA outputs syev3() allocates: n,
+    unless n * esize lies within 32.5 KiB of a multiple of 1 GiB (and is at
+    least 1 GiB); then the next stride whose byte length is 32.5 KiB past
+    that multiple."""
+    s = n * esize
+    r = s % _GIB
+    if s < _GIB or _STAGGER_BYTES <= r <= _GIB - _STAGGER_BYTES:
+        return n
+    return n + ((_STAGGER_BYTES - r) % _GIB) // esize
+
+
 def _dtype_code(t: torch.Tensor, refine: bool = True) -> int:
     if t.dtype == torch.float64:
         return F64
@@ -80,6 +113,22 @@ def _check_out(t, shape, strides, A, name):
         raise ValueError(f"out: {name} must be a {A.dtype} tensor of shape {shape} with "
                          f"strides {strides} on {A.device}, got {tuple(t.shape)}, "
                          f"{tuple(t.stride())}, {t.dtype}, {t.device}")
+
+
+def _check_out_soa(t, rows, n, A, name, ld=None):
+    """An SoA output: (rows, n), unit column stride, row stride >= n (ld
+    exactly, when the kernel takes the input's stride for every array)."""
+    if t is None:
+        raise ValueError(f"out: {name} is required")
+    if (t.dim() != 2 or tuple(t.shape) != (rows, n) or t.dtype != A.dtype
+            or t.device != A.device):
+        raise ValueError(f"out: {name} must be a {A.dtype} tensor of shape {(rows, n)} on "
+                         f"{A.device}, got {tuple(t.shape)}, {t.dtype}, {t.device}")
+    if n > 1 and t.stride(1) != 1:
+        raise ValueError(f"out: {name} must have unit column stride, got {tuple(t.stride())}")
+    if n > 0 and (t.stride(0) < n or (ld is not None and t.stride(0) != ld)):
+        want = f"row stride {ld}" if ld is not None else f"row stride >= n = {n}"
+        raise ValueError(f"out: {name} needs {want} (disjoint rows), got {tuple(t.stride())}")
 
 
 def _soa_geometry(A):
@@ -107,7 +156,9 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
 
     layout "soa": A has shape (6, n), rows a11 a12 a13 a22 a23 a33, row
     stride ld >= n (a slice of a (6, ld) buffer is fine).  Returns lam (3, n)
-    and V (9, n) with V[3*r + c, i] = row r of eigenvector c of matrix i.
+    and V (9, n) with V[3*r + c, i] = row r of eigenvector c of matrix i,
+    rows of one buffer whose row stride is out_stride(n, element size)
+    (n, except next to multiples of 1 GiB per plane).
     layout "aos": A has shape (n, 6), contiguous.  Returns lam (n, 3) and
     V (n, 3, 3) with columns the eigenvectors (as torch.linalg.eigh).
     layout "aos9": A holds full matrices, (n, 3, 3) or (n, 9), contiguous
@@ -116,8 +167,8 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
     with FP64 refinement (refine=False: the unrefined FP32 ablation,
     dtype F32).  vectors=False skips V.  info=True also returns the
     per-matrix branch and iteration counts (int32).
-    out: optional (lam, V) tensors to write into (same shapes as returned,
-    with the input's ld for SoA).
+    out: optional (lam, V) tensors to write into (same shapes as returned;
+    for SoA any row stride >= n, or exactly the input's with info=True).
     """
     if not A.is_cuda:
         raise ValueError("A must be a GPU tensor (the solver has no CPU path)")
@@ -125,17 +176,26 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
     if layout == "soa":
         n, ld = _soa_geometry(A)
         if out is None:
-            lam_buf = torch.empty((3, max(ld, 1)), dtype=A.dtype, device=A.device)
-            V_buf = (torch.empty((9, max(ld, 1)), dtype=A.dtype, device=A.device)
-                     if vectors else None)
-            lam, V = lam_buf[:, :n], (V_buf[:, :n] if vectors else None)
+            # one buffer of 3 (+ 9) planes; with info the kernel takes one
+            # stride for every array, the input's
+            ldo = ld if info else out_stride(n, A.element_size())
+            buf = torch.empty((12 if vectors else 3, max(ldo, 1)), dtype=A.dtype,
+                              device=A.device)
+            lam, V = buf[:3, :n], (buf[3:12, :n] if vectors else None)
         else:
             lam, V = out
-            _check_out(lam, (3, n), (ld, 1), A, "lam")
+            _check_out_soa(lam, 3, n, A, "lam", ld if info else None)
             if vectors:
-                _check_out(V, (9, n), (ld, 1), A, "V")
+                _check_out_soa(V, 9, n, A, "V", ld if info else None)
             else:
                 V = None
+        if not info:
+            rc = _lib.lib().batched_syev3_strided(
+                n, _ptr(A), ld, _ptr(lam), lam.stride(0) if n else 0, _ptr(V),
+                V.stride(0) if (V is not None and n) else 0, dt, flags,
+                _stream_handle(stream, A.device))
+            _lib.check(rc, "batched_syev3_strided")
+            return lam, V
         lay = SOA
     elif layout in ("aos", "aos9"):
         width = 6 if layout == "aos" else 9

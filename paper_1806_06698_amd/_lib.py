@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
     L.batched_syev3_inplace.restype = i32
     L.batched_syev3_info.argtypes = [i64, vp, i64, i32, vp, vp, i32, u32, vp, vp]
     L.batched_syev3_info.restype = i32
+    L.batched_syev3_strided.argtypes = [i64, vp, i64, vp, i64, vp, i64, i32, u32, vp]
+    L.batched_syev3_strided.restype = i32
     L.syev3_stream_reference.argtypes = [i64, vp, vp, vp, i32, vp]
     L.syev3_stream_reference.restype = i32
     L.syev3_stream_probe.argtypes = [i64, vp, vp, vp, i32, u32, vp]

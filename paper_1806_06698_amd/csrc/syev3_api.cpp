@@ -28,7 +28,9 @@ Range span(const void* p, int64_t n, int64_t ld, int layout, int planes,
   return r;
 }
 
-int check_args(int64_t n, const void* A, int64_t& ld, int layout,
+// ld: the SoA plane strides of A, lambda and V (0 means n), resolved here;
+// all 0 for AoS.
+int check_args(int64_t n, const void* A, syev3::Strides& ld, int layout,
                const void* lambda, const void* V, int dtype, uint32_t flags) {
   if (dtype != SYEV3_F64 && dtype != SYEV3_F32_REFINE && dtype != SYEV3_F32)
     return SYEV3_E_DTYPE;
@@ -43,10 +45,12 @@ int check_args(int64_t n, const void* A, int64_t& ld, int layout,
   // every element index (at most 9 planes of ld) must fit in int64 bytes
   const int64_t max_elems = (int64_t)(INT64_MAX / 16 / 9);
   if (layout == SYEV3_SOA) {
-    if (ld == 0) ld = n;
-    if (ld < n || ld > max_elems) return SYEV3_E_LAYOUT;
+    for (int64_t* s : {&ld.a, &ld.l, &ld.v}) {
+      if (*s == 0) *s = n;
+      if (*s < n || *s > max_elems) return SYEV3_E_LAYOUT;
+    }
   } else {
-    if (ld != 0) return SYEV3_E_LAYOUT;
+    if (ld.a != 0 || ld.l != 0 || ld.v != 0) return SYEV3_E_LAYOUT;
     if (n > max_elems) return SYEV3_E_N;
   }
   // the grid has one workgroup per 256 matrices
@@ -54,9 +58,9 @@ int check_args(int64_t n, const void* A, int64_t& ld, int layout,
   if (n == 0) return SYEV3_OK;
   if (!A || !lambda) return SYEV3_E_NULL;
   const size_t es = dtype == SYEV3_F64 ? sizeof(double) : sizeof(float);
-  const Range ra = span(A, n, ld, layout, layout == SYEV3_AOS9 ? 9 : 6, es);
-  const Range rl = span(lambda, n, ld, layout, 3, es);
-  const Range rv = span(V, n, ld, layout, 9, es);
+  const Range ra = span(A, n, ld.a, layout, layout == SYEV3_AOS9 ? 9 : 6, es);
+  const Range rl = span(lambda, n, ld.l, layout, 3, es);
+  const Range rv = span(V, n, ld.v, layout, 9, es);
   // in place: the full-matrix input may be overwritten by V exactly
   const bool inplace = layout == SYEV3_AOS9 && V == A;
   if (overlap(ra, rl) || (!inplace && overlap(ra, rv)) || overlap(rl, rv))
@@ -64,21 +68,17 @@ int check_args(int64_t n, const void* A, int64_t& ld, int layout,
   return SYEV3_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
-                       void* lambda, void* V, int dtype, uint32_t flags,
-                       int32_t* info, hipStream_t stream) {
+// Every entry point of the solver: checks, then the launch.
+int solve(int64_t n, const void* A, syev3::Strides ld, int layout, void* lambda, void* V,
+          int dtype, uint32_t flags, int32_t* info, hipStream_t stream) {
   const int rc = check_args(n, A, ld, layout, lambda, V, dtype, flags);
   if (rc != SYEV3_OK || n == 0) return rc;
   if (info) {
     const Range ri{(uintptr_t)info, (uintptr_t)info + (uintptr_t)n * sizeof(int32_t)};
     const size_t es = dtype == SYEV3_F64 ? sizeof(double) : sizeof(float);
-    if (overlap(ri, span(A, n, ld, layout, layout == SYEV3_AOS9 ? 9 : 6, es)) ||
-        overlap(ri, span(lambda, n, ld, layout, 3, es)) ||
-        overlap(ri, span(V, n, ld, layout, 9, es)))
+    if (overlap(ri, span(A, n, ld.a, layout, layout == SYEV3_AOS9 ? 9 : 6, es)) ||
+        overlap(ri, span(lambda, n, ld.l, layout, 3, es)) ||
+        overlap(ri, span(V, n, ld.v, layout, 9, es)))
       return SYEV3_E_ALIAS;
   }
   // The launchers read the launch status with hipGetLastError, which also
@@ -89,6 +89,24 @@ int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
   const hipError_t e = syev3::launch_batched(n, A, ld, layout, lambda, V, dtype,
                                              flags, info, stream);
   return e == hipSuccess ? SYEV3_OK : SYEV3_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
+                       void* lambda, void* V, int dtype, uint32_t flags,
+                       int32_t* info, hipStream_t stream) {
+  return solve(n, A, syev3::Strides{ld, ld, ld}, layout, lambda, V, dtype, flags, info,
+               stream);
+}
+
+int batched_syev3_strided(int64_t n, const void* A, int64_t lda, void* lambda, int64_t ldl,
+                          void* V, int64_t ldv, int dtype, uint32_t flags,
+                          hipStream_t stream) {
+  return solve(n, A, syev3::Strides{lda, ldl, ldv}, SYEV3_SOA, lambda, V, dtype, flags,
+               nullptr, stream);
 }
 
 int batched_syev3_ex(int64_t n, const void* A, int64_t ld, int layout,
@@ -114,7 +132,7 @@ int syev3_stream_probe(int64_t n, const void* A, void* lambda, void* V, int dtyp
   if ((mode & ~(SYEV3_PROBE_READ | SYEV3_PROBE_WRITE | SYEV3_PROBE_XCD_ORDER)) ||
       !(mode & (SYEV3_PROBE_READ | SYEV3_PROBE_WRITE)))
     return SYEV3_E_FLAGS;
-  int64_t ld = 0;
+  syev3::Strides ld{0, 0, 0};
   const int rc = check_args(n, A, ld, SYEV3_SOA, lambda, V, dtype, 0u);
   if (rc != SYEV3_OK || n == 0) return rc;
   if (n > ((int64_t)1 << 31)) return SYEV3_E_N;  // one launch

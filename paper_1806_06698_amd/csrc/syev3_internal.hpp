@@ -11,9 +11,14 @@ namespace syev3 {
 
 constexpr int kBlock = 256;  // lanes (matrices) per workgroup: 4 wavefronts
 
-// Launch the batched solver; arguments already validated.  Returns the HIP
-// status of the launch.
-hipError_t launch_batched(int64_t n, const void* A, int64_t ld, int layout,
+// Plane strides (elements) of the three SoA arrays; unused (0) for AoS.
+struct Strides {
+  int64_t a, l, v;
+};
+
+// Launch the batched solver; arguments already validated (SoA strides
+// resolved: each >= n).  Returns the HIP status of the launch.
+hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout,
                           void* lambda, void* V, int dtype, uint32_t flags,
                           int32_t* info, hipStream_t stream);
 

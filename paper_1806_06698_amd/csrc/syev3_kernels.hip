@@ -48,37 +48,54 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
   __builtin_nontemporal_store(v, p);
 }
 
-// T = double: FP64 path.  T = float: FP32 storage with FP64 refinement.
-template <typename T, bool VECS, bool INFO>
-__global__ __launch_bounds__(kBlock) void k_syev3_soa(
-    int64_t n, int64_t ld, const T* __restrict__ A, T* __restrict__ lam,
-    T* __restrict__ V, uint32_t flags, int32_t* __restrict__ info) {
-  const int64_t i = (int64_t)tile_of_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  if (i >= n) return;
-  double a[6];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream(A + k * ld + i);
-  double l[3], v[9];
-  const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v);
-#pragma unroll
-  for (int j = 0; j < 3; ++j) st_stream((T)l[j], lam + j * ld + i);
-  if (VECS) {
-#pragma unroll
-    for (int k = 0; k < 9; ++k) st_stream((T)v[k], V + k * ld + i);
-  }
-  if (INFO) info[i] = code;
+template <typename T>
+__device__ __forceinline__ T qnan() {
+  return (T)__builtin_nan("");
 }
 
-// The same with the 18 plane base addresses passed as kernel arguments
-// (uniform, held in scalar registers) and a 32-bit byte offset per lane, for
-// n * sizeof(T) < 2^32: loads and stores take the scalar-base addressing form
-// and need no 64-bit address arithmetic per lane.
+// The 18 plane base addresses of an SoA solve, passed as kernel arguments
+// (uniform, held in scalar registers): each array has a plane stride of its
+// own, so they may lie anywhere.
 template <typename T>
 struct Planes {
   const T* a[6];
   T* l[3];
   T* v[9];
 };
+
+// T = double: FP64 path.  T = float: FP32 storage with FP64 refinement.
+// 64-bit element offsets, for planes of more than 2^32 bytes.
+template <typename T, bool VECS, bool INFO>
+__global__ __launch_bounds__(kBlock) void k_syev3_soa(int64_t n, Planes<T> P, uint32_t flags,
+                                                     int32_t* __restrict__ info) {
+  const int64_t i = (int64_t)tile_of_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  double a[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream(P.a[k] + i);
+  double l[3], v[9];
+  bool bad;
+  const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v, bad);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) st_stream((T)l[j], P.l[j] + i);
+  if (VECS) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) st_stream((T)v[k], P.v[k] + i);
+  }
+  if (bad) {  // a NaN or infinite entry: NaN in every output of the matrix
+#pragma unroll
+    for (int j = 0; j < 3; ++j) st_stream(qnan<T>(), P.l[j] + i);
+    if (VECS) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) st_stream(qnan<T>(), P.v[k] + i);
+    }
+  }
+  if (INFO) info[i] = code;
+}
+
+// The same with a 32-bit byte offset per lane, for n * sizeof(T) < 2^32:
+// loads and stores take the scalar-base addressing form and need no 64-bit
+// address arithmetic per lane.
 
 template <typename T, bool VECS, bool INFO>
 __global__ __launch_bounds__(kBlock) void k_syev3_soa32(uint32_t n, Planes<T> P, uint32_t flags,
@@ -91,7 +108,8 @@ __global__ __launch_bounds__(kBlock) void k_syev3_soa32(uint32_t n, Planes<T> P,
   for (int k = 0; k < 6; ++k)
     a[k] = (double)ld_stream((const T*)((const char*)P.a[k] + off));
   double l[3], v[9];
-  const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v);
+  bool bad;
+  const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v, bad);
   // The offset is re-defined here (an empty asm emits nothing) so that the
   // stores, past the solve's branches, again see a 32-bit offset and take
   // the scalar-base form rather than a 64-bit address add per store: 12
@@ -103,6 +121,14 @@ __global__ __launch_bounds__(kBlock) void k_syev3_soa32(uint32_t n, Planes<T> P,
   if (VECS) {
 #pragma unroll
     for (int k = 0; k < 9; ++k) st_stream((T)v[k], (T*)((char*)P.v[k] + soff));
+  }
+  if (bad) {  // a NaN or infinite entry: NaN in every output of the matrix
+#pragma unroll
+    for (int j = 0; j < 3; ++j) st_stream(qnan<T>(), (T*)((char*)P.l[j] + soff));
+    if (VECS) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) st_stream(qnan<T>(), (T*)((char*)P.v[k] + soff));
+    }
   }
   if (INFO) info[i] = code;
 }
@@ -218,10 +244,15 @@ __global__ __launch_bounds__(kBlock) void k_syev3_aos(
   }
   __syncthreads();
   double l[3], v[9];
+  bool bad = false;
   if (t < cnt) {
-    const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v);
+    const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v, bad);
 #pragma unroll
     for (int j = 0; j < 3; ++j) sm[3 * t + j] = (T)l[j];
+    if (bad) {  // a NaN or infinite entry: NaN in every output of the matrix
+#pragma unroll
+      for (int j = 0; j < 3; ++j) sm[3 * t + j] = qnan<T>();
+    }
     if (INFO) info[base + t] = code;
   }
   __syncthreads();
@@ -232,6 +263,10 @@ __global__ __launch_bounds__(kBlock) void k_syev3_aos(
     if (t < cnt) {
 #pragma unroll
       for (int k = 0; k < 9; ++k) sm[9 * t + k] = (T)v[k];
+      if (bad) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) sm[9 * t + k] = qnan<T>();
+      }
     }
     __syncthreads();
     if (full) copy_out_full<T, kBlock * 9>(V + base * 9, sm, t);
@@ -240,21 +275,22 @@ __global__ __launch_bounds__(kBlock) void k_syev3_aos(
 }
 
 template <typename T, bool VECS, bool INFO>
-static hipError_t launch_t(int64_t n, const void* A, int64_t ld, int layout,
+static hipError_t launch_t(int64_t n, const void* A, Strides ld, int layout,
                            void* lambda, void* V, uint32_t flags, int32_t* info,
                            hipStream_t stream) {
   const int64_t blocks = (n + kBlock - 1) / kBlock;
   const dim3 grid((unsigned)blocks), block(kBlock);
-  if (layout == 0 && (uint64_t)n * sizeof(T) <= (uint64_t)UINT32_MAX) {
+  if (layout == 0) {
     Planes<T> P;
-    for (int k = 0; k < 6; ++k) P.a[k] = (const T*)A + k * ld;
-    for (int j = 0; j < 3; ++j) P.l[j] = (T*)lambda + j * ld;
-    for (int k = 0; k < 9; ++k) P.v[k] = VECS ? (T*)V + k * ld : nullptr;
-    hipLaunchKernelGGL((k_syev3_soa32<T, VECS, INFO>), grid, block, 0, stream, (uint32_t)n, P,
-                       flags, info);
-  } else if (layout == 0) {
-    hipLaunchKernelGGL((k_syev3_soa<T, VECS, INFO>), grid, block, 0, stream, n, ld,
-                       (const T*)A, (T*)lambda, (T*)V, flags, info);
+    for (int k = 0; k < 6; ++k) P.a[k] = (const T*)A + k * ld.a;
+    for (int j = 0; j < 3; ++j) P.l[j] = (T*)lambda + j * ld.l;
+    for (int k = 0; k < 9; ++k) P.v[k] = VECS ? (T*)V + k * ld.v : nullptr;
+    if ((uint64_t)n * sizeof(T) <= (uint64_t)UINT32_MAX)
+      hipLaunchKernelGGL((k_syev3_soa32<T, VECS, INFO>), grid, block, 0, stream, (uint32_t)n,
+                         P, flags, info);
+    else
+      hipLaunchKernelGGL((k_syev3_soa<T, VECS, INFO>), grid, block, 0, stream, n, P, flags,
+                         info);
   } else if (layout == 1) {
     hipLaunchKernelGGL((k_syev3_aos<T, 6, VECS, INFO>), grid, block, 0, stream, n,
                        (const T*)A, (T*)lambda, (T*)V, flags, info);
@@ -272,7 +308,7 @@ static hipError_t launch_t(int64_t n, const void* A, int64_t ld, int layout,
 constexpr int64_t kMaxPerLaunch = (int64_t)1 << 31;
 
 template <typename T>
-static hipError_t launch_dt(int64_t n, const void* A, int64_t ld, int layout,
+static hipError_t launch_dt(int64_t n, const void* A, Strides ld, int layout,
                             void* lambda, void* V, uint32_t flags, int32_t* info,
                             hipStream_t stream) {
   // elements per matrix between consecutive matrices: SoA planes are
@@ -298,7 +334,7 @@ static hipError_t launch_dt(int64_t n, const void* A, int64_t ld, int layout,
   return hipSuccess;
 }
 
-hipError_t launch_batched(int64_t n, const void* A, int64_t ld, int layout,
+hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout,
                           void* lambda, void* V, int dtype, uint32_t flags,
                           int32_t* info, hipStream_t stream) {
   if (dtype == 0)
@@ -324,15 +360,24 @@ __device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t i) 
 #pragma unroll
   for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream(A + k * lda + i);
   double l[3], v[9];
+  bool bad;
   if (V) {
-    solve3<true, std::is_same<T, float>::value>(a, s.flags, l, v);
+    solve3<true, std::is_same<T, float>::value>(a, s.flags, l, v, bad);
 #pragma unroll
     for (int k = 0; k < 9; ++k) st_stream((T)v[k], V + k * ld + i);
   } else {
-    solve3<false, std::is_same<T, float>::value>(a, s.flags, l, v);
+    solve3<false, std::is_same<T, float>::value>(a, s.flags, l, v, bad);
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j) st_stream((T)l[j], lam + j * ld + i);
+  if (bad) {  // a NaN or infinite entry: NaN in every output of the matrix
+#pragma unroll
+    for (int j = 0; j < 3; ++j) st_stream(qnan<T>(), lam + j * ld + i);
+    if (V) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) st_stream(qnan<T>(), V + k * ld + i);
+    }
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_syev3_segments(const TickTable* __restrict__ t) {

@@ -113,11 +113,17 @@ __device__ __forceinline__ double sqrt2(double x) {
 }
 
 // ---------------------------------------------------------------------------
-// 2x2 symmetric eigenproblem [[p, r], [r, q]] by one Jacobi rotation.
-// l1 >= l2; (k11, k21) is the unit eigenvector of l1, (k12, k22) that of l2.
-// t = sign(d) r / (|d| + hypot(d, r)), d = (q - p)/2, is the tangent of the
-// textbook rotation; c = 1/sqrt(1 + t^2), s = t c; J = [[c, s], [-s, c]]
-// gives J^T B J = diag(p - t r, q + t r).
+// 2x2 symmetric eigenproblem [[p, r], [r, q]] by one Jacobi rotation, the
+// textbook symmetric Schur rotation written so that it comes out ordered.
+// With d = (q - p)/2 and u = r / (|d| + hypot(d, r)) (|u| <= 1, the
+// rotation's tangent up to sign), the correction u r = r^2 / (|d| + hypot)
+// is >= 0 and
+//   l1 = max(p, q) + u r,  l2 = min(p, q) - u r  (l1 >= l2),
+// with unit eigenvector (c, u c) of l1 when p >= q, else (u c, c),
+// c = 1/sqrt(1 + u^2).  (From 2|d| D + r^2 = D^2, D = |d| + hypot(d, r).)
+// The eigenvector of l2 is that of l1 turned by 90 degrees, (-k21, k11), so
+// J = [[k11, k12], [k21, k22]] is a rotation with J^T B J = diag(l1, l2);
+// choosing the order costs two selects, not six.  Ties p == q keep (c, uc).
 // ---------------------------------------------------------------------------
 struct Rot2 {
   double l1, l2, k11, k12, k21, k22;
@@ -126,23 +132,21 @@ struct Rot2 {
 __device__ __forceinline__ Rot2 rot2(double p, double r, double q) {
   const double d = 0.5 * (q - p);
   const double ad = dabs(d);
-  double t = 0.0;
+  double u = 0.0;
   if (__builtin_fmax(ad, dabs(r)) >= 0x1p-500) {
     const double rr = sqrt2(__builtin_fma(d, d, r * r));
-    t = ddiv(d >= 0.0 ? r : -r, ad + rr);
+    u = ddiv(r, ad + rr);
   }
-  const double c = rsqrt2(__builtin_fma(t, t, 1.0));
-  const double s = t * c;
-  const double a1 = __builtin_fma(-t, r, p);
-  const double a2 = __builtin_fma(t, r, q);
+  const double c = rsqrt2(__builtin_fma(u, u, 1.0));
+  const double s = u * c;
+  const bool keep = p >= q;
   Rot2 o;
-  const bool keep = a1 >= a2;
-  o.l1 = keep ? a1 : a2;
-  o.l2 = keep ? a2 : a1;
+  o.l1 = __builtin_fma(u, r, __builtin_fmax(p, q));
+  o.l2 = __builtin_fma(-u, r, __builtin_fmin(p, q));
   o.k11 = keep ? c : s;
-  o.k12 = keep ? s : c;
-  o.k21 = keep ? -s : c;
-  o.k22 = keep ? c : -s;
+  o.k21 = keep ? s : c;
+  o.k12 = -o.k21;
+  o.k22 = o.k11;
   return o;
 }
 
@@ -260,7 +264,8 @@ __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
 //    [L, U] and its zero is a new upper bound U.
 //  * Tangent of 1/(x + ab) at U: it lies below the function everywhere, so
 //    the same construction gives a function above f and a new lower bound L.
-//  * A second chord over the narrowed [L, U] gives the start.
+//  * A second chord over the narrowed [L, U] gives the start (PAIRS such
+//    tangent-and-chord pairs after the first chord).
 // Each bound is the positive zero of (1 + w) x^2 - c x - b1^2, w the line's
 // slope times -b2^2.  The constants c = gb + b2^2 * (the line's value at 0)
 // are written as c0 + b2^2 ((value at 0) - 1/ab), with c0 = gb + b2^2/ab
@@ -275,6 +280,7 @@ __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
 // finite); otherwise the FP64 bounds of bg_start.  The start may fall on
 // either side of the zero by FP32 rounding; the step handles both.
 // rab = 1/ab.
+template <int PAIRS>
 __device__ __forceinline__ double start_point(const Arrow1& P, double rab) {
   const Arrow1f Q{(float)P.b1s, (float)P.b2s, (float)P.ab, (float)P.gb};
   const bool ok = Q.b1s >= 0x1p-120f && Q.b2s >= 0x1p-120f && Q.ab >= 0x1p-100f;
@@ -286,15 +292,22 @@ __device__ __forceinline__ double start_point(const Arrow1& P, double rab) {
   float ru = __builtin_amdgcn_rcpf(U + Q.ab);
   float w = Q.b2s * rl * ru;
   U = __builtin_fminf(U, quad_zero32(c0 - w * (L * U) * rabf, Q.b1s, 1.0f + w));
-  ru = __builtin_amdgcn_rcpf(U + Q.ab);
-  w = Q.b2s * ru * ru;
-  L = __builtin_fmaxf(L, quad_zero32(c0 - w * (U * U) * rabf, Q.b1s, 1.0f + w));
-  rl = __builtin_amdgcn_rcpf(L + Q.ab);
-  w = Q.b2s * rl * ru;
-  U = __builtin_fminf(U, quad_zero32(c0 - w * (L * U) * rabf, Q.b1s, 1.0f + w));
+#pragma unroll
+  for (int j = 0; j < PAIRS; ++j) {
+    ru = __builtin_amdgcn_rcpf(U + Q.ab);
+    w = Q.b2s * ru * ru;
+    L = __builtin_fmaxf(L, quad_zero32(c0 - w * (U * U) * rabf, Q.b1s, 1.0f + w));
+    rl = __builtin_amdgcn_rcpf(L + Q.ab);
+    w = Q.b2s * rl * ru;
+    U = __builtin_fminf(U, quad_zero32(c0 - w * (L * U) * rabf, Q.b1s, 1.0f + w));
+  }
   if (ok && U >= 0x1p-124f && U < 0x1p100f) return (double)U;
   return bg_start(P, rab);
 }
+
+// Tangent-and-chord pairs of the two starts (mu, nu).
+constexpr int kStartPairsMu = 1;
+constexpr int kStartPairsNu = 2;
 
 // One Borges-Gragg step from x on either side of the zero (Sec. 1.4.1: the
 // iteration converges monotonically from any start in (0, inf)).  Sets stop
@@ -436,8 +449,8 @@ __device__ __forceinline__ double newton_step(const Arrow1& P, double x, bool& s
 __device__ __forceinline__ void zeros_bg(const Arrow1& P1, const Arrow1& P2,
                                          double& x1, double& x2, int& it1, int& it2) {
   const double rab = rcp1(P1.ab);  // both problems share abar
-  x1 = start_point(P1, rab);
-  x2 = start_point(P2, rab);
+  x1 = start_point<kStartPairsMu>(P1, rab);
+  x2 = start_point<kStartPairsNu>(P2, rab);
   bool s1 = false, s2 = false;
   it1 = 0;
   it2 = 0;
@@ -545,7 +558,11 @@ __device__ __forceinline__ double newton_refine(const Arrow1& P, double x, bool&
 // finder with FP64 refinement and an FP64 re-orthogonalisation; with
 // kFlagUnrefined the FP32 zeros are used as they are, with the paper's
 // vector formulas (zeros the FP32 finder cannot give still go to FP64 BG).
-// Returns branch | it_mu << 8 | it_nu << 16.
+// Returns branch | it_mu << 8 | it_nu << 16.  bad is set for a matrix with
+// a NaN or infinite entry: its outputs are then meaningless (the solve runs
+// on the non-finite values, every loop bounded) and the caller stores NaN in
+// their place, in a branch that costs nothing when no lane of the wavefront
+// takes it.
 // ---------------------------------------------------------------------------
 struct Vec3 {
   double x, y, z;
@@ -567,13 +584,17 @@ __device__ __forceinline__ Vec3 axpy(double s, const Vec3& a, const Vec3& b) {
 
 template <bool VECS, bool F32R>
 __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
-                                      double (&lam)[3], double (&V)[9]) {
+                                      double (&lam)[3], double (&V)[9], bool& bad) {
   double a11 = ain[0], a12 = ain[1], a13 = ain[2], a22 = ain[3], a23 = ain[4],
          a33 = ain[5];
   const bool finite = __builtin_isfinite(a11) && __builtin_isfinite(a12) &&
                       __builtin_isfinite(a13) && __builtin_isfinite(a22) &&
                       __builtin_isfinite(a23) && __builtin_isfinite(a33);
-  if (!finite) { a11 = a12 = a13 = a22 = a23 = a33 = 0.0; }
+  // Kept as a word from here on: left as a condition the compiler re-derives
+  // it at the stores from the six inputs, holding them through the solve.
+  uint32_t badw = finite ? 0u : 1u;
+  asm volatile("" : "+v"(badw));
+  bad = badw != 0u;
   const double m = __builtin_fmax(__builtin_fmax(__builtin_fmax(dabs(a11), dabs(a12)),
                                                  __builtin_fmax(dabs(a13), dabs(a22))),
                                   __builtin_fmax(dabs(a23), dabs(a33)));
@@ -727,36 +748,39 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
       v2 = normalized(u1);
       v0 = normalized(u3);
       if (F32R && !(flags & kFlagUnrefined)) {
-        // one Gram-Schmidt re-orthogonalisation: u3 against u1, then the
-        // middle vector as their cross product (the paper's u2 is u1 x u3
-        // up to a positive factor), orthogonal to both by construction
+        // one Gram-Schmidt re-orthogonalisation: u3 against u1
         v0 = normalized(axpy(-dot(v2, v0), v2, v0));
-        v1 = Vec3{__builtin_fma(v2.y, v0.z, -v2.z * v0.y), __builtin_fma(v2.z, v0.x, -v2.x * v0.z),
-                  __builtin_fma(v2.x, v0.y, -v2.y * v0.x)};
-      } else {
+      }
+      if (F32R && (flags & kFlagUnrefined)) {
+        // the ablation keeps the paper's formula for u2
         const Vec3 u2{-be2 * mu * nua, be1 * nu * mua, be1 * be2 * al};
         v1 = normalized(u2);
+      } else {
+        // The paper's u2 is (mu + nu + abar) (u1 x u3), a positive multiple
+        // of the cross product (expand u1 x u3 and factor), so the middle
+        // vector is taken as the cross product of the two unit vectors:
+        // orthogonal to both by construction, and 15 operations cheaper
+        // than forming and normalising u2.
+        v1 = Vec3{__builtin_fma(v2.y, v0.z, -v2.z * v0.y), __builtin_fma(v2.z, v0.x, -v2.x * v0.z),
+                  __builtin_fma(v2.x, v0.y, -v2.y * v0.x)};
       }
     }
   }
 
-  // a matrix with a non-finite entry was solved as zero; adding NaN marks
-  // every output (adding 0.0 elsewhere changes at most the sign of a zero)
-  const double poison = finite ? 0.0 : __builtin_nan("");
-  lam[0] = __builtin_amdgcn_ldexp(l0, e) + poison;
-  lam[1] = __builtin_amdgcn_ldexp(l1, e) + poison;
-  lam[2] = __builtin_amdgcn_ldexp(l2, e) + poison;
+  lam[0] = __builtin_amdgcn_ldexp(l0, e);
+  lam[1] = __builtin_amdgcn_ldexp(l1, e);
+  lam[2] = __builtin_amdgcn_ldexp(l2, e);
   if (VECS) {
     // back to A's coordinates: V = diag(J, 1) [v0 v1 v2]
-    V[0] = __builtin_fma(J.k11, v0.x, __builtin_fma(J.k12, v0.y, poison));
-    V[1] = __builtin_fma(J.k11, v1.x, __builtin_fma(J.k12, v1.y, poison));
-    V[2] = __builtin_fma(J.k11, v2.x, __builtin_fma(J.k12, v2.y, poison));
-    V[3] = __builtin_fma(J.k21, v0.x, __builtin_fma(J.k22, v0.y, poison));
-    V[4] = __builtin_fma(J.k21, v1.x, __builtin_fma(J.k22, v1.y, poison));
-    V[5] = __builtin_fma(J.k21, v2.x, __builtin_fma(J.k22, v2.y, poison));
-    V[6] = v0.z + poison;
-    V[7] = v1.z + poison;
-    V[8] = v2.z + poison;
+    V[0] = __builtin_fma(J.k11, v0.x, J.k12 * v0.y);
+    V[1] = __builtin_fma(J.k11, v1.x, J.k12 * v1.y);
+    V[2] = __builtin_fma(J.k11, v2.x, J.k12 * v2.y);
+    V[3] = __builtin_fma(J.k21, v0.x, J.k22 * v0.y);
+    V[4] = __builtin_fma(J.k21, v1.x, J.k22 * v1.y);
+    V[5] = __builtin_fma(J.k21, v2.x, J.k22 * v2.y);
+    V[6] = v0.z;
+    V[7] = v1.z;
+    V[8] = v2.z;
   }
   if (!finite) {
     branch = kNonFinite;

@@ -20,7 +20,7 @@
 namespace {
 struct Launch {
   int count = 0;
-  int64_t n, ld;
+  int64_t n, ld, ldl, ldv;
   int layout, dtype;
   const void* A;
   void* lam;
@@ -31,14 +31,15 @@ struct Launch {
 }  // namespace
 
 namespace syev3 {
-hipError_t launch_batched(int64_t n, const void* A, int64_t ld, int layout, void* lambda,
+hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout, void* lambda,
                           void* V, int dtype, uint32_t flags, int32_t* info, hipStream_t) {
-  g_launch = Launch{g_launch.count + 1, n, ld, layout, dtype, A, lambda, V, flags, info};
+  g_launch = Launch{g_launch.count + 1, n, ld.a, ld.l, ld.v, layout, dtype, A, lambda, V,
+                    flags, info};
   return hipSuccess;
 }
 hipError_t launch_stream_probe(int64_t n, const void* A, void* lambda, void* V, int dtype,
                                uint32_t, hipStream_t) {
-  g_launch = Launch{g_launch.count + 1, n, n, 0, dtype, A, lambda, V, 0u, nullptr};
+  g_launch = Launch{g_launch.count + 1, n, n, n, n, 0, dtype, A, lambda, V, 0u, nullptr};
   return hipSuccess;
 }
 }  // namespace syev3
@@ -63,8 +64,9 @@ Span span_of(uint64_t p, int64_t n, int64_t ld, int layout, int planes, int es) 
 }
 
 // The documented rules, for |n|, |ld| < 2^40 (far from the size limit).
-bool model_valid(int64_t n, uint64_t A, int64_t ld, int layout, uint64_t lam, uint64_t V,
-                 int dtype, uint32_t flags, uint64_t info, bool allow_inplace) {
+bool model_valid(int64_t n, uint64_t A, int64_t ld, int64_t ldl, int64_t ldv, int layout,
+                 uint64_t lam, uint64_t V, int dtype, uint32_t flags, uint64_t info,
+                 bool allow_inplace) {
   if (dtype < 0 || dtype > 2) return false;
   if (flags & ~63u) return false;
   if ((flags & 12u) && dtype != 0) return false;  // Newton, paper BG: FP64 only
@@ -74,16 +76,18 @@ bool model_valid(int64_t n, uint64_t A, int64_t ld, int layout, uint64_t lam, ui
   if (n < 0) return false;
   if (layout == 0) {
     if (ld == 0) ld = n;
-    if (ld < n) return false;
-  } else if (ld != 0) {
+    if (ldl == 0) ldl = n;
+    if (ldv == 0) ldv = n;
+    if (ld < n || ldl < n || ldv < n) return false;
+  } else if (ld != 0 || ldl != 0 || ldv != 0) {
     return false;
   }
   if (n == 0) return true;
   if (!A || !lam) return false;
   const int es = dtype == 0 ? 8 : 4;
   const Span a = span_of(A, n, ld, layout, layout == 2 ? 9 : 6, es);
-  const Span l = span_of(lam, n, ld, layout, 3, es);
-  const Span v = span_of(V, n, ld, layout, 9, es);
+  const Span l = span_of(lam, n, ldl, layout, 3, es);
+  const Span v = span_of(V, n, ldv, layout, 9, es);
   const bool inplace = allow_inplace && layout == 2 && V == A;
   if (hits(a, l) || (!inplace && hits(a, v)) || hits(l, v)) return false;
   if (info) {
@@ -113,15 +117,20 @@ int main(int argc, char** argv) {
     int64_t n = far ? pick({-3, 0, 1, 2, 255, 256, 257, 1000, 65536 + 7, 1 << 20})
                     : pick({big, big - 1, big / 2, big / 144, big / 143, (int64_t)1 << 40,
                             ((int64_t)1 << 32) * 256, INT64_MIN, -1});
-    int64_t ld = pick({0, 0, 0, 1, 2});
-    switch (rng() % 5) {
-      case 0: ld = 0; break;
-      case 1: ld = n; break;
-      case 2: ld = n > big - 5 ? n : n + (int64_t)(rng() % 5); break;
-      case 3: ld = n == INT64_MIN ? n : n - 1; break;
-      default: ld = far ? (int64_t)(rng() % 3000000) : pick({big, big / 8, INT64_MIN});
-    }
-    if (far && (ld > ((int64_t)1 << 40) || ld < -((int64_t)1 << 40))) ld = 0;
+    auto draw_ld = [&]() {
+      int64_t ld = 0;
+      switch (rng() % 5) {
+        case 0: ld = 0; break;
+        case 1: ld = n; break;
+        case 2: ld = n > big - 5 ? n : n + (int64_t)(rng() % 5); break;
+        case 3: ld = n == INT64_MIN ? n : n - 1; break;
+        default: ld = far ? (int64_t)(rng() % 3000000) : pick({big, big / 8, INT64_MIN});
+      }
+      if (far && (ld > ((int64_t)1 << 40) || ld < -((int64_t)1 << 40))) ld = 0;
+      return ld;
+    };
+    // one stride for every array, and two more for the strided entry point
+    const int64_t ld = draw_ld(), ld_l = draw_ld(), ld_v = draw_ld();
     const int layout = (int)pick({0, 0, 1, 2, -1, 3});
     const int dtype = (int)pick({0, 0, 1, 2, -1, 3});
     const uint32_t flags = (uint32_t)pick({0, 0, 0, 1, 2, 4, 7, 8, 12, 15, 16, 17, 19, 31, 32, 33, 63, 64,
@@ -136,13 +145,13 @@ int main(int argc, char** argv) {
       }
     };
     uint64_t A = addr(0), L = addr(1), V = addr(2), F = rng() % 3 == 0 ? addr(3) : 0;
-    const int which = (int)(rng() % 5);
+    const int which = (int)(rng() % 6);
     if (which == 3 && rng() % 2) V = A;  // in place
     g_launch.count = 0;
     int rc;
     bool allow_inplace = true;
     uint64_t info = 0;
-    int64_t exp_ld = ld;
+    int64_t exp_ld = ld, exp_ldl = ld, exp_ldv = ld;
     int exp_layout = layout;
     uint32_t exp_flags = flags;
     int64_t mn = n;
@@ -165,13 +174,22 @@ int main(int argc, char** argv) {
         rc = batched_syev3_inplace(n, (void*)A, (void*)L, dtype, nullptr);
         V = A; exp_ld = 0; exp_layout = 2; exp_flags = 0; mlayout = 2; mflags = 0;
         break;
+      case 5:  // SoA with a stride per array
+        rc = batched_syev3_strided(n, (void*)A, ld, (void*)L, ld_l, (void*)V, ld_v, dtype, flags,
+                                   nullptr);
+        exp_ldl = ld_l; exp_ldv = ld_v; exp_layout = 0; mlayout = 0;
+        allow_inplace = false;
+        break;
       default:
         rc = syev3_stream_reference(n, (void*)A, (void*)L, (void*)V, dtype, nullptr);
         exp_ld = 0; exp_layout = 0; exp_flags = 0; mlayout = 0; mflags = 0;
         allow_inplace = false;
         break;
     }
-    const int64_t mld = (which == 1 || which == 2) ? ld : 0;
+    const bool strided_args = which == 1 || which == 2 || which == 5;
+    if (which != 5) exp_ldl = exp_ldv = exp_ld;  // one stride for all arrays
+    const int64_t mld = strided_args ? ld : 0;
+    const int64_t mldl = which == 5 ? ld_l : mld, mldv = which == 5 ? ld_v : mld;
     // accepted <=> launched (n > 0) or a no-op (n == 0)
     const bool launched = g_launch.count == 1;
     n_launched += launched;
@@ -183,16 +201,19 @@ int main(int argc, char** argv) {
     if (rc != SYEV3_OK && launched) fail("rejected but launched", i);
     if (rc != SYEV3_OK && (rc > -1 || rc < -7 || rc == SYEV3_E_HIP)) fail("undocumented code", i);
     if (launched) {
-      const int64_t want_ld = exp_layout == 0 ? (exp_ld == 0 ? mn : exp_ld) : 0;
+      auto want = [&](int64_t s) { return exp_layout == 0 ? (s == 0 ? mn : s) : 0; };
+      const int64_t want_ld = want(exp_ld);
       if (g_launch.n != mn || (uint64_t)g_launch.A != A || (uint64_t)g_launch.lam != L ||
           (uint64_t)g_launch.V != V || g_launch.dtype != dtype)
         fail("launcher got other pointers or sizes", i);
-      if (which != 4 && (g_launch.ld != want_ld || g_launch.layout != exp_layout ||
+      if (which != 4 && (g_launch.ld != want_ld || g_launch.ldl != want(exp_ldl) ||
+                         g_launch.ldv != want(exp_ldv) || g_launch.layout != exp_layout ||
                          (g_launch.flags & 63u) != exp_flags || (uint64_t)g_launch.info != info))
         fail("launcher got another layout, stride, flags or info", i);
     }
     if (far) {
-      const bool ok = model_valid(mn, A, mld, mlayout, L, V, dtype, mflags, info, allow_inplace);
+      const bool ok = model_valid(mn, A, mld, mldl, mldv, mlayout, L, V, dtype, mflags, info,
+                                  allow_inplace);
       if (ok != (rc == SYEV3_OK)) fail(ok ? "valid call rejected" : "invalid call accepted", i);
     }
   }

@@ -642,8 +642,62 @@ def test_explicit_stream_and_fp32_plane_stride():
     W[:, :n] = A[:, :n].float()
     lam_s, V_s = solve_soa(W[:, :n])
     lam_c, V_c = solve_soa(W[:, :n].contiguous())
-    assert lam_s.stride(0) == ld
+    assert lam_s.stride(0) == s3.out_stride(n, 4)
     assert torch.equal(lam_s, lam_c) and torch.equal(V_s, V_c)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_a_stride_per_array(dtype):
+    """batched_syev3_strided: input, eigenvalues and vectors each with a
+    plane stride of its own (including the binding's staggered output
+    buffer) give the bits of the one-stride call; the results meet the
+    oracle's bars; arrays whose plane ranges interleave are refused."""
+    import ctypes
+    n = 70_001
+    A = gen.stress_mix(n, 63, "cuda")[0].to(dtype)
+    lam_ref, V_ref = s3.syev3(A, info=True)[:2]        # one stride (info path)
+    sh = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    dt = s3.F64 if dtype == torch.float64 else s3.F32_REFINE
+    for lda, ldl, ldv in ((n, n + 3, n + 70), (n + 1000, n, n + 4160), (2 * n, 3 * n, n)):
+        Ab = torch.full((6, lda), float("nan"), dtype=dtype, device="cuda")
+        Ab[:, :n] = A
+        lb = torch.full((3, ldl), float("nan"), dtype=dtype, device="cuda")
+        vb = torch.full((9, ldv), float("nan"), dtype=dtype, device="cuda")
+        rc = s3.batched_syev3_strided(n, ctypes.c_void_p(Ab.data_ptr()), lda,
+                                      ctypes.c_void_p(lb.data_ptr()), ldl,
+                                      ctypes.c_void_p(vb.data_ptr()), ldv, dt, 0, sh)
+        assert rc == 0
+        torch.cuda.synchronize()
+        assert torch.equal(lb[:, :n], lam_ref) and torch.equal(vb[:, :n], V_ref)
+        # the gaps between planes are not written
+        assert torch.isnan(lb[:, n:]).all() and torch.isnan(vb[:, n:]).all()
+    # the binding's default: one staggered buffer for lam and V
+    lam, V = s3.syev3(A)
+    torch.cuda.synchronize()
+    assert torch.equal(lam, lam_ref) and torch.equal(V, V_ref)
+    check_vs_oracle(A, lam, V, f32=dtype == torch.float32, sample=20_000, label="strided")
+    # lam's three planes interleaved with V's: refused even though no plane overlaps
+    buf = torch.empty((12, n), dtype=dtype, device="cuda")
+    rc = s3.batched_syev3_strided(n, ctypes.c_void_p(A.data_ptr()), n,
+                                  ctypes.c_void_p(buf.data_ptr()), 4 * n,
+                                  ctypes.c_void_p(buf[1].data_ptr()), n, dt, 0, sh)
+    assert rc == -5
+
+
+def test_binding_staggers_outputs_at_1_gib_planes():
+    """With planes of exactly 1 GiB (2^27 FP64 matrices) the binding lays
+    the outputs out with a plane stride of n plus 32.5 KiB; the results
+    are those of contiguous outputs."""
+    n = 1 << 27
+    A = gen.normal(n, 64, "cuda")
+    lam, _ = s3.syev3(A, vectors=False)
+    assert lam.stride(0) == n + 4160
+    lam_c = torch.empty((3, n), dtype=torch.float64, device="cuda")
+    s3.syev3(A, vectors=False, out=(lam_c, None))
+    torch.cuda.synchronize()
+    assert torch.equal(lam, lam_c)
+    del A, lam, lam_c
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
