@@ -57,8 +57,6 @@ def parse():
                    help="time only the headline workload (for profiler runs)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-serving", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=12.0,
-                   help="target CPU time of the oracle baseline sample")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only a plain device copy of 2^30 bytes (known traffic), "
                         "to calibrate the FETCH_SIZE/WRITE_SIZE counters")
@@ -147,42 +145,55 @@ def host_info():
     return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
-def cpu_baseline(torch, gen, target_s):
-    """The oracle, as it is, on the host's cores: a fixed sample of the
-    headline workload's matrices, solved repeatedly until about target_s
-    seconds have passed."""
+def cpu_baseline(torch, gen, sample_1core=1 << 20):
+    """The oracle, as it is, on the host's cores, on the same seeded inputs
+    as the GPU workloads (drawn on the device and copied to the host):
+    every configuration whole on all threads (the 2^28 batch in 2^24-matrix
+    chunks, so that host memory stays bounded), and the first
+    `sample_1core` matrices of each on one thread.  Eigenvalues and
+    eigenvectors, FP64."""
     import oracle
     oracle.build(force=False)
     threads = oracle.default_threads()
-    m = 1 << 22
-    A = gen.spd_fe(m, seed=2, device="cpu")
-    A6 = gen.to_aos(A).numpy()
-    oracle.solve(A6[: 1 << 16], nthreads=threads)  # warm the thread pool
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        oracle.solve(A6, nthreads=threads)
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= target_s:
-            break
-    # one core: the first 2^18 matrices of the same sample, about 3 s
-    m1 = 1 << 18
-    reps1, t1 = 0, time.perf_counter()
-    while True:
-        oracle.solve(A6[:m1], nthreads=1)
-        reps1 += 1
-        dt1 = time.perf_counter() - t1
-        if dt1 >= min(3.0, target_s):
-            break
-    return {"value": reps * m / dt, "unit": "eigensolves/s (vals+vecs)", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{m} matrices of the SPD workload's generator (CPU draw, seed 2), "
-                      f"FP64 vals+vecs, solved {reps} times in {dt:.1f} s on {threads} "
-                      f"threads",
+    chunk = 1 << 24
+
+    def solve_rate(A_dev, nthreads, limit=None):
+        n = A_dev.shape[1] if limit is None else min(limit, A_dev.shape[1])
+        t = 0.0
+        for s in range(0, n, chunk):
+            A6 = A_dev[:, s:min(n, s + chunk)].t().contiguous().cpu().numpy()
+            t0 = time.perf_counter()
+            oracle.solve(A6, nthreads=nthreads)
+            t += time.perf_counter() - t0
+            del A6
+        return n / t, t
+
+    oracle.solve(gen.to_aos(gen.normal(1 << 16, 0)).numpy(), nthreads=threads)  # warm
+    configs = {}
+    for name, (kind, n, seed) in {
+            "normal_4k": ("normal", 4096, 0),
+            "stress_mix_16m": ("stress_mix", 1 << 24, 1),
+            "spd_fe_64m": ("spd_fe", 1 << 26, 2),
+            "wide_range_256m": ("wide_range", 1 << 28, 4)}.items():
+        A = gen.make(kind, n, seed, "cuda")[0]
+        torch.cuda.synchronize()
+        rate, t = solve_rate(A, threads)
+        rate1, t1 = solve_rate(A, 1, limit=sample_1core)
+        configs[name] = {"n": n, "eigensolves_per_s": rate, "seconds": t,
+                         "threads": threads,
+                         "eigensolves_per_s_1_thread": rate1, "seconds_1_thread": t1,
+                         "n_1_thread": min(n, sample_1core)}
+        del A
+        torch.cuda.empty_cache()
+    head = configs["spd_fe_64m"]
+    return {"value": head["eigensolves_per_s"], "unit": "eigensolves/s (vals+vecs)",
+            "cores": threads, "kind": "oracle",
+            "sample": f"the whole 2^26-matrix SPD workload (seed 2), FP64 vals+vecs, "
+                      f"{head['seconds']:.1f} s on {threads} threads",
             "host": host_info(),
-            "value_1_core": reps1 * m1 / dt1,
-            "sample_1_core": f"the first {m1} of those matrices, solved {reps1} times in "
-                             f"{dt1:.1f} s on 1 thread"}
+            "value_1_core": head["eigensolves_per_s_1_thread"],
+            "sample_1_core": f"its first {head['n_1_thread']} matrices on 1 thread",
+            "per_config": configs}
 
 
 def f32r_errors(torch, gen, s3, n_sample=200_000, refine=True, flags=0):
@@ -252,7 +263,7 @@ def main():
     # start from an idle device, not from whatever ran just before this
     # process (after large allocations and heavy traffic the memory system
     # has been seen slower for a few seconds).
-    cpu = None if args.no_cpu_baseline else cpu_baseline(torch, gen, args.cpu_seconds)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(torch, gen)
     dev = "cuda"
     n = 1 << 26
     khash = kernel_hash()
@@ -410,7 +421,18 @@ def main():
         A, _ = gen.wide_range(1 << 28, seed=4, device=dev)
         run_variant("wide_range_256m_f64_soa", A, "soa", True, "f64", steps=5)
         run_variant("wide_range_256m_f64_soa_valsonly", A, "soa", False, "f64", steps=5)
+        # the same input in a (6, ld) buffer whose plane stride is the
+        # binding's output stride (n + 4160 here): no plane a multiple of
+        # 1 GiB from another
+        nn = A.shape[1]
+        ld = s3.out_stride(nn, 8)
+        Ab = torch.empty((6, ld), dtype=torch.float64, device=dev)
+        Ab[:, :nn].copy_(A)
         del A
+        torch.cuda.empty_cache()
+        run_variant("wide_range_256m_f64_soa_staggered", Ab[:, :nn], "soa", True, "f64",
+                    steps=5)
+        del Ab
         torch.cuda.empty_cache()
         A, _ = gen.wide_range(1 << 28, seed=4, device=dev)
         Aa = A.t().contiguous()
@@ -419,6 +441,10 @@ def main():
         run_variant("wide_range_256m_f64_aos", Aa, "aos", True, "f64", steps=5)
         del Aa
         torch.cuda.empty_cache()
+        aos_ms = side["wide_range_256m_f64_aos"].get("ms_per_launch")
+        for k in ("wide_range_256m_f64_soa", "wide_range_256m_f64_soa_staggered"):
+            ms = side[k].get("ms_per_launch")
+            side[k + "_over_aos_time"] = ms / aos_ms if ms and aos_ms else None
         line["variants"] = side
         try:
             line["f32r_error_vs_fp64_oracle"] = f32r_errors(torch, gen, s3)

@@ -265,32 +265,46 @@ class Server:
 
 def bench(duration_s=4.0, budget_bytes=64 << 30, seed=3):
     """Serving measurement: request sizes 2^U(0,20) from the stress mix, 50%
-    FP64 / 50% FP32-storage.  First the saturated rate (closed loop, 64
-    requests in flight), then open-loop Poisson arrivals at 50% and 80% of
-    that rate, and at a low fixed rate (2000 requests/s, about one request
-    per tick: the latency floor of the path)."""
+    FP64 / 50% FP32-storage, eigenvalues and vectors.  Requests read their
+    input in place from a resident pool (input views): only their outputs
+    take pool memory, so the client side costs little and the figures are
+    the server's.
+      * saturation: closed loop, 256 requests in flight;
+      * open-loop Poisson arrivals at 50% and 80% of that rate;
+      * a low fixed rate (2000 requests/s, about one request per tick): the
+        latency floor of the path;
+      * budget pressure: a closed loop deep enough (16384 requests) that the
+        64 GiB pool fills and admissions are refused, with p50/p99 there;
+      * for comparison, requests whose input is copied into the pool on the
+        device (64 in flight) and host-staged requests (pinned host memory
+        in and out, 64 in flight)."""
     from . import gen
     src_n = 1 << 20
     A, _ = gen.stress_mix(src_n, seed=seed, device="cuda")
     Af = A.float().contiguous()
     torch.cuda.synchronize()
     out = {"workload": "Poisson arrivals; n = floor(2^U(0,20)) stress-mix matrices per "
-                       "request; 50% FP64 / 50% FP32-storage; vals+vecs; inputs copied "
-                       "on the device from a resident pool; HBM budget "
+                       "request; 50% FP64 / 50% FP32-storage; vals+vecs; inputs read in place "
+                       "from a resident pool (views) unless stated; HBM budget "
                        f"{budget_bytes / 2**30:.0f} GiB",
            "latency": "arrival to observed completion (includes waiting for admission)"}
     with Server(hbm_budget_bytes=budget_bytes) as srv:
-        sat = srv.loadgen(A, Af, qps=0.0, concurrency=64,
-                          duration_s=min(2.0, duration_s), seed=seed)
-        out["closed_loop_64_in_flight"] = sat
+        sat = srv.loadgen(A, Af, qps=0.0, concurrency=256, duration_s=min(2.0, duration_s),
+                          seed=seed, input_views=True)
+        out["closed_loop_256_in_flight"] = sat
         rate = sat["requests_per_s"]
         for rho in (0.5, 0.8):
-            r = srv.loadgen(A, Af, qps=rho * rate, duration_s=duration_s, seed=seed + 1)
+            r = srv.loadgen(A, Af, qps=rho * rate, duration_s=duration_s, seed=seed + 1,
+                            input_views=True)
             r["offered_qps"] = rho * rate
             out[f"open_loop_{int(rho * 100)}pct"] = r
-        r = srv.loadgen(A, Af, qps=2000.0, duration_s=min(1.0, duration_s), seed=seed + 3)
+        r = srv.loadgen(A, Af, qps=2000.0, duration_s=min(1.0, duration_s), seed=seed + 3,
+                        input_views=True)
         r["offered_qps"] = 2000.0
         out["open_loop_2000qps"] = r
+        r = srv.loadgen(A, Af, qps=0.0, concurrency=64, duration_s=min(1.0, duration_s),
+                        seed=seed + 4)
+        out["copied_inputs_closed_loop_64_in_flight"] = r
         # host-staged: inputs from pinned host memory, results back to it
         m = 1 << 20
         hA = A[:, :m].cpu().contiguous().pin_memory()
@@ -300,4 +314,12 @@ def bench(duration_s=4.0, budget_bytes=64 << 30, seed=3):
                         seed=seed + 2, sink=sink)
         out["host_staged_closed_loop_64_in_flight"] = r
         out["server_stats"] = srv.stats()
+    # a server with room for enough requests to fill its pool
+    with Server(hbm_budget_bytes=budget_bytes, max_requests=16384) as srv:
+        r = srv.loadgen(A, Af, qps=0.0, concurrency=16384, duration_s=min(2.0, duration_s),
+                        seed=seed + 5, input_views=True)
+        st = srv.stats()
+        r["acquire_rejections"] = st["acquire_rejections"]
+        r["pool_bytes_peak_over_budget"] = st["pool_bytes_peak"] / budget_bytes
+        out["budget_pressure_closed_loop_16384"] = r
     return out
