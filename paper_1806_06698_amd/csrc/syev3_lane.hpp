@@ -342,8 +342,16 @@ __device__ __forceinline__ double bg_update(const Arrow1& P, double x, const Spe
   const double b = __builtin_fma(s.f, s.rx, s.fp);
   const double disc = __builtin_fmax(0x1p-1000, __builtin_fma(b, b, 4.0 * a * s.f));
   const double sq = sqrt1(disc);
-  const bool conj = b < 0.0;
-  const double dl = (conj ? sq - b : 2.0 * s.f) * rcp1(conj ? 2.0 * a : b + sq);
+  double dl = (2.0 * s.f) * rcp1(b + sq);
+  if (b < 0.0) {
+    // the conjugate form, only far left of the zero (f/x < -f'); in a
+    // branch of its own (the empty asm keeps the compiler from evaluating
+    // it on every lane and selecting), as no lane takes it after a start
+    // close to the zero
+    double bb = b;
+    asm volatile("" : "+v"(bb));
+    dl = (sq - bb) * rcp1(2.0 * a);
+  }
   double xn;
   if (dl <= 0.5 * x) {
     xn = x - dl;
@@ -577,6 +585,19 @@ __device__ __forceinline__ Vec3 normalized(Vec3 u) {
   return Vec3{u.x * r, u.y * r, u.z * r};
 }
 
+// 1/sqrt(x) to ~2^-47 for normal x > 0: one Goldschmidt step.
+__device__ __forceinline__ double rsqrt1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double g = x * y, h = 0.5 * y;
+  return 2.0 * __builtin_fma(h, __builtin_fma(-g, h, 0.5), h);
+}
+
+// Unit vector to ~2^-47, for vectors stored in FP32.
+__device__ __forceinline__ Vec3 normalized_f32out(Vec3 u) {
+  const double r = rsqrt1(dot(u, u));
+  return Vec3{u.x * r, u.y * r, u.z * r};
+}
+
 __device__ __forceinline__ Vec3 axpy(double s, const Vec3& a, const Vec3& b) {
   return Vec3{__builtin_fma(s, a.x, b.x), __builtin_fma(s, a.y, b.y),
               __builtin_fma(s, a.z, b.z)};
@@ -625,12 +646,14 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
   const double cg = be2 * rh;  // G = [[cg, -sg, 0], [sg, cg, 0], [0, 0, 1]]
   const double sg = be1 * rh;
   const double al = al1 - al2;
-  const bool small_s = dabs(sg) <= dabs(cg);
-  const double s2 = sg * sg, c2 = cg * cg;
-  const double d1 = small_s ? __builtin_fma(-al, s2, al1) : __builtin_fma(al, c2, al2);
-  const double d2 = small_s ? __builtin_fma(al, s2, al2) : __builtin_fma(-al, c2, al1);
+  // The test's right-hand side needs d1 and d2 only to a few ulps of the
+  // larger alpha: alpha1 - alpha s^2 and alpha2 + alpha s^2 serve.  The
+  // deflated branch forms them exactly (below).
+  const double s2 = sg * sg;
   const double ee = al * sg * cg;
-  const double rhs = (flags & kFlagSimplified) ? dabs(al1 + al2) : dabs(d1) + dabs(d2);
+  const double rhs = (flags & kFlagSimplified)
+                         ? dabs(al1 + al2)
+                         : dabs(__builtin_fma(-al, s2, al1)) + dabs(__builtin_fma(al, s2, al2));
   const bool defl = !diag && dabs(ee) <= kEps64 * rhs;
 
   double l0, l1, l2;  // ascending
@@ -643,6 +666,12 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
     if (defl) {
       // accept d1 with G^T e1 = (cg, -sg, 0); solve [[d2, h], [h, gamma]]
       branch = kDeflated;
+      // d1, d2 with the smaller correction: bitwise exact for the beta- and
+      // combo-deflations (sg or cg zero, or alpha zero)
+      const bool small_s = dabs(sg) <= dabs(cg);
+      const double c2 = cg * cg;
+      const double d1 = small_s ? __builtin_fma(-al, s2, al1) : __builtin_fma(al, c2, al2);
+      const double d2 = small_s ? __builtin_fma(al, s2, al2) : __builtin_fma(-al, c2, al1);
       const Rot2 T = rot2(d2, h, ga);
       lx = T.l1;
       ly = T.l2;
@@ -745,11 +774,14 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
       const double mua = mu + al, nua = nu + al;
       const Vec3 u1{be1 * mua, be2 * mu, mu * mua};
       const Vec3 u3{be1 * nu, be2 * nua, -nu * nua};
-      v2 = normalized(u1);
-      v0 = normalized(u3);
       if (F32R && !(flags & kFlagUnrefined)) {
-        // one Gram-Schmidt re-orthogonalisation: u3 against u1
-        v0 = normalized(axpy(-dot(v2, v0), v2, v0));
+        // FP32 outputs: units to ~2^-47, and one Gram-Schmidt
+        // re-orthogonalisation of u3 against u1 before u3 is normalised
+        v2 = normalized_f32out(u1);
+        v0 = normalized_f32out(axpy(-dot(v2, u3), v2, u3));
+      } else {
+        v2 = normalized(u1);
+        v0 = normalized(u3);
       }
       if (F32R && (flags & kFlagUnrefined)) {
         // the ablation keeps the paper's formula for u2
