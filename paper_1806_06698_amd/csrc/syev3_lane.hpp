@@ -59,9 +59,10 @@ enum Branch : int { kZero = 0, kNonFinite = 1, kDiagonal = 2, kDeflated = 3,
 
 // ---------------------------------------------------------------------------
 // Arithmetic primitives.  gfx950's v_rcp_f64, v_rsq_f64 and v_sqrt_f64 are
-// accurate to about 2^-24 (measured); Newton-Raphson / Goldschmidt steps
-// built from FMAs bring them to the rounding level at a fraction of the cost
-// of the IEEE-exact division and square-root sequences.  Arguments must be
+// accurate to about 2^-24 (measured); Newton-Raphson, Goldschmidt or
+// third-order correction steps built from FMAs bring them to the rounding
+// level at a fraction of the cost of the IEEE-exact division and square-root
+// sequences.  Arguments must be
 // normal positive numbers (or, for rcp, any normal non-zero number).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double dabs(double x) { return __builtin_fabs(x); }
@@ -81,17 +82,15 @@ __device__ __forceinline__ double div_r(double a, double b, double rb) {
 
 __device__ __forceinline__ double ddiv(double a, double b) { return div_r(a, b, rcp1(b)); }
 
-// 1/sqrt(x) to about one ulp: v_rsq_f64 and two Goldschmidt steps
-// (g -> sqrt(x), h -> 1/(2 sqrt(x))).
+// 1/sqrt(x) to about one ulp: v_rsq_f64 and one third-order correction.
+// With e = 1 - x y^2, 1/sqrt(x) = y (1 - e)^(-1/2) = y (1 + e/2 + 3e^2/8 +
+// 5e^3/16 + ...); for |e| ~ 2^-23 the neglected terms are below 2^-66, and
+// e itself is formed by one FMA from x y, so the result carries the
+// roundings of the last FMA and of e's product, under one ulp together.
 __device__ __forceinline__ double rsqrt2(double x) {
   const double y = __builtin_amdgcn_rsq(x);
-  double g = x * y, h = 0.5 * y;
-  double r = __builtin_fma(-g, h, 0.5);
-  g = __builtin_fma(g, r, g);
-  h = __builtin_fma(h, r, h);
-  r = __builtin_fma(-g, h, 0.5);
-  h = __builtin_fma(h, r, h);
-  return 2.0 * h;
+  const double e = __builtin_fma(-(x * y), y, 1.0);
+  return __builtin_fma(y, e * __builtin_fma(e, 0.375, 0.5), y);
 }
 
 // sqrt(x) to ~2^-47 for normal x > 0: one Goldschmidt step.
@@ -240,6 +239,13 @@ __device__ __forceinline__ float quad_zero32(float c, float k, float a) {
   return (pos ? s : k) * __builtin_amdgcn_rcpf(pos ? a : s);
 }
 
+// The same for a = 1: positive zero of x^2 - c x - k.
+__device__ __forceinline__ float quad_zero32_1(float c, float k) {
+  const float c2 = 0.5f * c;
+  const float s = __builtin_fabsf(c2) + __builtin_amdgcn_sqrtf(__builtin_fmaf(c2, c2, k));
+  return c >= 0.0f ? s : k * __builtin_amdgcn_rcpf(s);
+}
+
 // The FP64 path's two-chord bounds (bg_start) in FP32; the chords' constant
 // is c0, which FP32 could not form where its terms cancel.
 __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
@@ -286,8 +292,8 @@ __device__ __forceinline__ double start_point(const Arrow1& P, double rab) {
   const bool ok = Q.b1s >= 0x1p-120f && Q.b2s >= 0x1p-120f && Q.ab >= 0x1p-100f;
   const float c0 = (float)__builtin_fma(P.b2s, rab, P.gb);
   const float rabf = __builtin_amdgcn_rcpf(Q.ab);
-  float L = quad_zero32(Q.gb, Q.b1s, 1.0f);
-  float U = quad_zero32(Q.gb, Q.b1s + Q.b2s, 1.0f);
+  float L = quad_zero32_1(Q.gb, Q.b1s);
+  float U = quad_zero32_1(Q.gb, Q.b1s + Q.b2s);
   float rl = __builtin_amdgcn_rcpf(L + Q.ab);
   float ru = __builtin_amdgcn_rcpf(U + Q.ab);
   float w = Q.b2s * rl * ru;
@@ -329,18 +335,19 @@ constexpr int kStartPairsNu = 2;
 //    decreases): x_new - zero < (w0 - 1)|D|^3 / (x_new (x_new + ab) f'(x_j)),
 //    cubic in the step and checked without evaluating f at x_new.  Left of
 //    it: zero - x_new < |f(x_new)| / f'(c) <= |f(x_new)| (f' >= 1, the bound
-//    of Sec. 1.4.2).  Either is compared with 2 eps x_new.  A step that does
-//    not move x towards the zero (rounding at the zero) stops with x.
+//    of Sec. 1.4.2).  Either is compared with 2 eps x_new.  A step that
+//    rounding at the zero leaves in place, or moves by an ulp the wrong way,
+//    passes it too.
 // D is computed to about 2^-46: near the zero a cubic step's own error must
 // stay below the rounding level.
 __device__ __forceinline__ double bg_update(const Arrow1& P, double x, const Spec& s,
                                             bool& stop) {
   const bool left = s.f < 0.0;
   const double w0m1 = (s.q2 * P.ab) * (s.rp * s.rp);
-  const double w0 = w0m1 + 1.0;
-  const double a = -w0 * s.rx;
   const double b = __builtin_fma(s.f, s.rx, s.fp);
-  const double disc = __builtin_fmax(0x1p-1000, __builtin_fma(b, b, 4.0 * a * s.f));
+  // 4 a f, with -4 w0 = -4 w0m1 - 4 in one FMA (bitwise the same product)
+  const double a4f = (__builtin_fma(w0m1, -4.0, -4.0) * s.rx) * s.f;
+  const double disc = __builtin_fmax(0x1p-1000, __builtin_fma(b, b, a4f));
   const double sq = sqrt1(disc);
   double dl = (2.0 * s.f) * rcp1(b + sq);
   if (b < 0.0) {
@@ -348,8 +355,9 @@ __device__ __forceinline__ double bg_update(const Arrow1& P, double x, const Spe
     // branch of its own (the empty asm keeps the compiler from evaluating
     // it on every lane and selecting), as no lane takes it after a start
     // close to the zero
-    double bb = b;
-    asm volatile("" : "+v"(bb));
+    double bb = b, wm = w0m1;
+    asm volatile("" : "+v"(bb), "+v"(wm));
+    const double a = -(wm + 1.0) * s.rx;
     dl = (sq - bb) * rcp1(2.0 * a);
   }
   double xn;
@@ -357,18 +365,20 @@ __device__ __forceinline__ double bg_update(const Arrow1& P, double x, const Spe
     xn = x - dl;
   } else {
     // right of the zero, a step of more than half of x: the model zero
+    double wm = w0m1;
+    asm volatile("" : "+v"(wm));
+    const double w0 = wm + 1.0;
     const double r = x * s.rp;
     const double w1 = __builtin_fma(P.b2s * r, r * r, P.b1s);
     const double sigma = (w0 * x - w1 * s.rx) - s.f;
     const double sq2 = sqrt2(__builtin_fma(sigma, sigma, 4.0 * w0 * w1));
     xn = sigma >= 0.0 ? ddiv(sigma + sq2, 2.0 * w0) : ddiv(2.0 * w1, sq2 - sigma);
   }
-  if (left ? !(xn > x) : !(xn < x)) {
-    stop = true;
-    return x;
-  }
+  // Written as "not above", so that a NaN stops the iteration.  A step
+  // that rounding at the zero sends the wrong way is below the rounding
+  // level and passes the test.
   const double D = dabs(x - xn);
-  if (w0m1 * (D * D) * D <= 2.0 * kEps64 * (xn * xn) * (xn + P.ab) * (left ? 1.0 : s.fp))
+  if (!(w0m1 * (D * D) * D > 2.0 * kEps64 * (xn * xn) * (xn + P.ab) * (left ? 1.0 : s.fp)))
     stop = true;
   return xn;
 }
@@ -585,19 +595,6 @@ __device__ __forceinline__ Vec3 normalized(Vec3 u) {
   return Vec3{u.x * r, u.y * r, u.z * r};
 }
 
-// 1/sqrt(x) to ~2^-47 for normal x > 0: one Goldschmidt step.
-__device__ __forceinline__ double rsqrt1(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
-  const double g = x * y, h = 0.5 * y;
-  return 2.0 * __builtin_fma(h, __builtin_fma(-g, h, 0.5), h);
-}
-
-// Unit vector to ~2^-47, for vectors stored in FP32.
-__device__ __forceinline__ Vec3 normalized_f32out(Vec3 u) {
-  const double r = rsqrt1(dot(u, u));
-  return Vec3{u.x * r, u.y * r, u.z * r};
-}
-
 __device__ __forceinline__ Vec3 axpy(double s, const Vec3& a, const Vec3& b) {
   return Vec3{__builtin_fma(s, a.x, b.x), __builtin_fma(s, a.y, b.y),
               __builtin_fma(s, a.z, b.z)};
@@ -621,7 +618,14 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
                                   __builtin_fmax(dabs(a23), dabs(a33)));
   // scale by 2^-e so that max |a_ij| is in [1/2, 1); m == 0 keeps e = 0
   // (kFlagNoScale, a uniform flag: e = 0, the unscaled matrix)
-  const int e = __builtin_amdgcn_frexp_exp(m) & ((flags & kFlagNoScale) ? 0 : ~0);
+  // (The flags are the same for every lane: their alternatives are taken in
+  // uniform branches, which the empty asm keeps the compiler from turning
+  // into per-lane selects that every lane would pay for.)
+  int e = __builtin_amdgcn_frexp_exp(m);
+  if (flags & kFlagNoScale) {
+    asm volatile("");
+    e = 0;
+  }
   a11 = __builtin_amdgcn_ldexp(a11, -e);
   a12 = __builtin_amdgcn_ldexp(a12, -e);
   a13 = __builtin_amdgcn_ldexp(a13, -e);
@@ -640,7 +644,13 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
   // h <= eps (|alpha1| + |alpha2| + |gamma|) is tested as h^2 <= (eps ...)^2.
   const double hh = __builtin_fma(be1, be1, be2 * be2);
   const double tol_h = kEps64 * (dabs(al1) + dabs(al2) + dabs(ga));
-  const bool diag = (flags & kFlagNoHGuard) ? (hh == 0.0) : !(hh > tol_h * tol_h);
+  bool diag;
+  if (flags & kFlagNoHGuard) {
+    asm volatile("");
+    diag = hh == 0.0;
+  } else {
+    diag = !(hh > tol_h * tol_h);
+  }
   const double rh = rsqrt2(hh);  // unused (inf/NaN) on diagonal lanes
   const double h = hh * rh;
   const double cg = be2 * rh;  // G = [[cg, -sg, 0], [sg, cg, 0], [0, 0, 1]]
@@ -651,9 +661,13 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
   // deflated branch forms them exactly (below).
   const double s2 = sg * sg;
   const double ee = al * sg * cg;
-  const double rhs = (flags & kFlagSimplified)
-                         ? dabs(al1 + al2)
-                         : dabs(__builtin_fma(-al, s2, al1)) + dabs(__builtin_fma(al, s2, al2));
+  double rhs;
+  if (flags & kFlagSimplified) {
+    asm volatile("");
+    rhs = dabs(al1 + al2);
+  } else {
+    rhs = dabs(__builtin_fma(-al, s2, al1)) + dabs(__builtin_fma(al, s2, al2));
+  }
   const bool defl = !diag && dabs(ee) <= kEps64 * rhs;
 
   double l0, l1, l2;  // ascending
@@ -775,10 +789,10 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
       const Vec3 u1{be1 * mua, be2 * mu, mu * mua};
       const Vec3 u3{be1 * nu, be2 * nua, -nu * nua};
       if (F32R && !(flags & kFlagUnrefined)) {
-        // FP32 outputs: units to ~2^-47, and one Gram-Schmidt
-        // re-orthogonalisation of u3 against u1 before u3 is normalised
-        v2 = normalized_f32out(u1);
-        v0 = normalized_f32out(axpy(-dot(v2, u3), v2, u3));
+        // one Gram-Schmidt re-orthogonalisation of u3 against the unit u1,
+        // before u3 is normalised
+        v2 = normalized(u1);
+        v0 = normalized(axpy(-dot(v2, u3), v2, u3));
       } else {
         v2 = normalized(u1);
         v0 = normalized(u3);
