@@ -48,6 +48,11 @@ __device__ __forceinline__ void st_stream(T v, T* p) {
   __builtin_nontemporal_store(v, p);
 }
 
+// The element type a form stores: double for FP64, float for both FP32
+// forms.
+template <int FORM>
+using Storage = typename std::conditional<FORM == kFormF64, double, float>::type;
+
 template <typename T>
 __device__ __forceinline__ T qnan() {
   return (T)__builtin_nan("");
@@ -65,9 +70,10 @@ struct Planes {
 
 // T = double: FP64 path.  T = float: FP32 storage with FP64 refinement.
 // 64-bit element offsets, for planes of more than 2^32 bytes.
-template <typename T, bool VECS, bool INFO>
-__global__ __launch_bounds__(kBlock) void k_syev3_soa(int64_t n, Planes<T> P, uint32_t flags,
-                                                     int32_t* __restrict__ info) {
+template <int FORM, bool VECS, bool INFO>
+__global__ __launch_bounds__(kBlock) void k_syev3_soa(int64_t n, Planes<Storage<FORM>> P,
+                                                     uint32_t flags, int32_t* __restrict__ info) {
+  using T = Storage<FORM>;
   const int64_t i = (int64_t)tile_of_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   if (i >= n) return;
   double a[6];
@@ -75,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_syev3_soa(int64_t n, Planes<T> P, ui
   for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream(P.a[k] + i);
   double l[3], v[9];
   bool bad;
-  const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v, bad);
+  const int code = solve3<VECS, FORM>(a, flags, l, v, bad);
 #pragma unroll
   for (int j = 0; j < 3; ++j) st_stream((T)l[j], P.l[j] + i);
   if (VECS) {
@@ -97,9 +103,10 @@ __global__ __launch_bounds__(kBlock) void k_syev3_soa(int64_t n, Planes<T> P, ui
 // loads and stores take the scalar-base addressing form and need no 64-bit
 // address arithmetic per lane.
 
-template <typename T, bool VECS, bool INFO>
-__global__ __launch_bounds__(kBlock) void k_syev3_soa32(uint32_t n, Planes<T> P, uint32_t flags,
-                                                       int32_t* __restrict__ info) {
+template <int FORM, bool VECS, bool INFO>
+__global__ __launch_bounds__(kBlock) void k_syev3_soa32(uint32_t n, Planes<Storage<FORM>> P,
+                                                       uint32_t flags, int32_t* __restrict__ info) {
+  using T = Storage<FORM>;
   const uint32_t i = tile_of_block(blockIdx.x, gridDim.x) * (uint32_t)kBlock + threadIdx.x;
   if (i >= n) return;
   const uint32_t off = i * (uint32_t)sizeof(T);  // byte offset within a plane
@@ -109,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_syev3_soa32(uint32_t n, Planes<T> P,
     a[k] = (double)ld_stream((const T*)((const char*)P.a[k] + off));
   double l[3], v[9];
   bool bad;
-  const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v, bad);
+  const int code = solve3<VECS, FORM>(a, flags, l, v, bad);
   // The offset is re-defined here (an empty asm emits nothing) so that the
   // stores, past the solve's branches, again see a 32-bit offset and take
   // the scalar-base form rather than a 64-bit address add per store: 12
@@ -215,10 +222,11 @@ __device__ __forceinline__ void copy_out(T* g, const T* sm, int total, int t) {
 // rounds, lambda and then V, so the buffer holds 9 values per matrix rather
 // than 12: 18 KB per workgroup in FP64, which lets 8 waves per SIMD fit in
 // the 160 KB of LDS (24 KB allowed only 6).
-template <typename T, int IN, bool VECS, bool INFO>
+template <int FORM, int IN, bool VECS, bool INFO>
 __global__ __launch_bounds__(kBlock) void k_syev3_aos(
-    int64_t n, const T* A, T* __restrict__ lam, T* V, uint32_t flags,
-    int32_t* __restrict__ info) {
+    int64_t n, const Storage<FORM>* A, Storage<FORM>* __restrict__ lam, Storage<FORM>* V,
+    uint32_t flags, int32_t* __restrict__ info) {
+  using T = Storage<FORM>;
   __shared__ __attribute__((aligned(16))) T sm[kBlock * 9];
   const int64_t base = (int64_t)tile_of_block(blockIdx.x, gridDim.x) * kBlock;
   const int cnt = (int)((n - base) < kBlock ? (n - base) : kBlock);
@@ -246,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_syev3_aos(
   double l[3], v[9];
   bool bad = false;
   if (t < cnt) {
-    const int code = solve3<VECS, std::is_same<T, float>::value>(a, flags, l, v, bad);
+    const int code = solve3<VECS, FORM>(a, flags, l, v, bad);
 #pragma unroll
     for (int j = 0; j < 3; ++j) sm[3 * t + j] = (T)l[j];
     if (bad) {  // a NaN or infinite entry: NaN in every output of the matrix
@@ -274,10 +282,11 @@ __global__ __launch_bounds__(kBlock) void k_syev3_aos(
   }
 }
 
-template <typename T, bool VECS, bool INFO>
+template <int FORM, bool VECS, bool INFO>
 static hipError_t launch_t(int64_t n, const void* A, Strides ld, int layout,
                            void* lambda, void* V, uint32_t flags, int32_t* info,
                            hipStream_t stream) {
+  using T = Storage<FORM>;
   const int64_t blocks = (n + kBlock - 1) / kBlock;
   const dim3 grid((unsigned)blocks), block(kBlock);
   if (layout == 0) {
@@ -286,16 +295,16 @@ static hipError_t launch_t(int64_t n, const void* A, Strides ld, int layout,
     for (int j = 0; j < 3; ++j) P.l[j] = (T*)lambda + j * ld.l;
     for (int k = 0; k < 9; ++k) P.v[k] = VECS ? (T*)V + k * ld.v : nullptr;
     if ((uint64_t)n * sizeof(T) <= (uint64_t)UINT32_MAX)
-      hipLaunchKernelGGL((k_syev3_soa32<T, VECS, INFO>), grid, block, 0, stream, (uint32_t)n,
+      hipLaunchKernelGGL((k_syev3_soa32<FORM, VECS, INFO>), grid, block, 0, stream, (uint32_t)n,
                          P, flags, info);
     else
-      hipLaunchKernelGGL((k_syev3_soa<T, VECS, INFO>), grid, block, 0, stream, n, P, flags,
+      hipLaunchKernelGGL((k_syev3_soa<FORM, VECS, INFO>), grid, block, 0, stream, n, P, flags,
                          info);
   } else if (layout == 1) {
-    hipLaunchKernelGGL((k_syev3_aos<T, 6, VECS, INFO>), grid, block, 0, stream, n,
+    hipLaunchKernelGGL((k_syev3_aos<FORM, 6, VECS, INFO>), grid, block, 0, stream, n,
                        (const T*)A, (T*)lambda, (T*)V, flags, info);
   } else {
-    hipLaunchKernelGGL((k_syev3_aos<T, 9, VECS, INFO>), grid, block, 0, stream, n,
+    hipLaunchKernelGGL((k_syev3_aos<FORM, 9, VECS, INFO>), grid, block, 0, stream, n,
                        (const T*)A, (T*)lambda, (T*)V, flags, info);
   }
   return hipGetLastError();
@@ -307,10 +316,11 @@ static hipError_t launch_t(int64_t n, const void* A, Strides ld, int layout,
 // by its own lane, so the split changes no result.
 constexpr int64_t kMaxPerLaunch = (int64_t)1 << 31;
 
-template <typename T>
+template <int FORM>
 static hipError_t launch_dt(int64_t n, const void* A, Strides ld, int layout,
                             void* lambda, void* V, uint32_t flags, int32_t* info,
                             hipStream_t stream) {
+  using T = Storage<FORM>;
   // elements per matrix between consecutive matrices: SoA planes are
   // offset as a whole (ld is unchanged), AoS rows are packed
   const int64_t w_in = layout == 0 ? 1 : (layout == 1 ? 6 : 9);
@@ -323,11 +333,11 @@ static hipError_t launch_dt(int64_t n, const void* A, Strides ld, int layout,
     int32_t* is = info ? info + s : nullptr;
     hipError_t e;
     if (V) {
-      e = info ? launch_t<T, true, true>(m, As, ld, layout, ls, Vs, flags, is, stream)
-               : launch_t<T, true, false>(m, As, ld, layout, ls, Vs, flags, is, stream);
+      e = info ? launch_t<FORM, true, true>(m, As, ld, layout, ls, Vs, flags, is, stream)
+               : launch_t<FORM, true, false>(m, As, ld, layout, ls, Vs, flags, is, stream);
     } else {
-      e = info ? launch_t<T, false, true>(m, As, ld, layout, ls, Vs, flags, is, stream)
-               : launch_t<T, false, false>(m, As, ld, layout, ls, Vs, flags, is, stream);
+      e = info ? launch_t<FORM, false, true>(m, As, ld, layout, ls, Vs, flags, is, stream)
+               : launch_t<FORM, false, false>(m, As, ld, layout, ls, Vs, flags, is, stream);
     }
     if (e != hipSuccess) return e;
   }
@@ -337,10 +347,11 @@ static hipError_t launch_dt(int64_t n, const void* A, Strides ld, int layout,
 hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout,
                           void* lambda, void* V, int dtype, uint32_t flags,
                           int32_t* info, hipStream_t stream) {
-  if (dtype == 0)
-    return launch_dt<double>(n, A, ld, layout, lambda, V, flags, info, stream);
-  if (dtype == 2) flags |= kFlagUnrefined;
-  return launch_dt<float>(n, A, ld, layout, lambda, V, flags, info, stream);
+  if (dtype == kFormF64)
+    return launch_dt<kFormF64>(n, A, ld, layout, lambda, V, flags, info, stream);
+  if (dtype == kFormF32R)
+    return launch_dt<kFormF32R>(n, A, ld, layout, lambda, V, flags, info, stream);
+  return launch_dt<kFormF32>(n, A, ld, layout, lambda, V, flags, info, stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -350,8 +361,9 @@ hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout,
 // binary search of the (small) table, so each wavefront runs one dtype and
 // one code path.  Per-matrix arithmetic is exactly the batched kernels'.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <int FORM>
 __device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t i) {
+  using T = Storage<FORM>;
   const T* A = (const T*)s.A;
   T* lam = (T*)s.lambda;
   T* V = (T*)s.V;
@@ -362,11 +374,11 @@ __device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t i) 
   double l[3], v[9];
   bool bad;
   if (V) {
-    solve3<true, std::is_same<T, float>::value>(a, s.flags, l, v, bad);
+    solve3<true, FORM>(a, s.flags, l, v, bad);
 #pragma unroll
     for (int k = 0; k < 9; ++k) st_stream((T)v[k], V + k * ld + i);
   } else {
-    solve3<false, std::is_same<T, float>::value>(a, s.flags, l, v, bad);
+    solve3<false, FORM>(a, s.flags, l, v, bad);
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j) st_stream((T)l[j], lam + j * ld + i);
@@ -393,8 +405,9 @@ __global__ __launch_bounds__(kBlock) void k_syev3_segments(const TickTable* __re
     const Segment s = t->seg[lo];
     const int64_t i = (tile - s.tile_begin) * kBlock + threadIdx.x;
     if (i < s.n) {
-      if (s.dtype == 0) solve_segment_tile<double>(s, i);
-      else solve_segment_tile<float>(s, i);
+      // the server admits the FP64 and the refined FP32 form
+      if (s.dtype == kFormF64) solve_segment_tile<kFormF64>(s, i);
+      else solve_segment_tile<kFormF32R>(s, i);
     }
   }
 }

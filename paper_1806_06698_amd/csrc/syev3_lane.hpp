@@ -50,9 +50,15 @@ constexpr uint32_t kFlagNewton = 4u;
 constexpr uint32_t kFlagPaperBG = 8u;
 constexpr uint32_t kFlagRefineConverge = 16u;
 constexpr uint32_t kFlagNoScale = 32u;
-// internal: FP32 zero finder without the FP64 Newton step and without the
-// re-orthogonalisation (an ablation of the refinement); never set by callers
-constexpr uint32_t kFlagUnrefined = 1u << 31;
+
+// Arithmetic forms of the solve, a template argument (equal to the dtype
+// codes of the interface): FP64 throughout; FP32 storage with FP64
+// refinement; FP32 storage with the FP32 zero finder's zeros used as they
+// are and no re-orthogonalisation (an ablation of the refinement).  Each
+// form is compiled on its own, so no form's kernel holds another's code.
+constexpr int kFormF64 = 0;
+constexpr int kFormF32R = 1;
+constexpr int kFormF32 = 2;
 
 enum Branch : int { kZero = 0, kNonFinite = 1, kDiagonal = 2, kDeflated = 3,
                     kReduced = 4 };
@@ -204,6 +210,12 @@ __device__ __forceinline__ double quad_zero(double c, double k, double a) {
 }
 
 constexpr int kChords = 2;
+// Chords of the FP32-storage form's start, before its one FP32 step.  In a
+// CPU emulation, the Newton step's check then sends 6% of SPD wavefronts
+// and 1% of N(0,1) ones to FP64 Borges-Gragg with three chords, 34% and 20%
+// with two; iterating FP32 to its own stop test instead takes a second
+// FP32 trip in 89% and 99% of wavefronts.
+constexpr int kChordsRefine = 3;
 
 __device__ __forceinline__ double bg_start(const Arrow1& P, double rab) {
   double U = quad_zero(P.gb, P.b1s + P.b2s, 1.0);
@@ -219,14 +231,15 @@ __device__ __forceinline__ double bg_start(const Arrow1& P, double rab) {
 }
 
 // FP32 versions (v_rcp_f32 and v_sqrt_f32 are accurate to about one ulp),
-// for the FP32 zero finder of the FP32-storage form and for the start of the
-// FP64 iteration.  That start only has to be close: the iteration converges
-// from either side (bg_step), and a start within about 1e-5 of the zero
-// still needs a single evaluation of f in FP64.  FP32 is cheaper than the
-// FP64 sequences, and the FP64 path is limited as much by the clock the
-// chip sustains under FP64 load as by HBM.
+// for the start of the FP64 iteration and of the FP32-storage form's Newton
+// step, and for the FP32 zero finder of the unrefined FP32 ablation.  The
+// FP64 iteration's start only has to be close: it converges from either
+// side (bg_step), and a start within about 1e-5 of the zero still needs a
+// single evaluation of f in FP64.  FP32 is cheaper than the FP64 sequences,
+// and the FP64 path is limited as much by the clock the chip sustains under
+// FP64 load as by HBM.
 // c0 = gb + b2^2/ab and rab = 1/ab, formed in FP64 and rounded, for the
-// FP32 zero finder of the FP32-storage form (unused by start_point).
+// FP32 zero finder of the unrefined form (unused by start_point).
 struct Arrow1f {
   float b1s, b2s, ab, gb;
   float c0 = 0.0f, rab = 0.0f;
@@ -246,14 +259,15 @@ __device__ __forceinline__ float quad_zero32_1(float c, float k) {
   return c >= 0.0f ? s : k * __builtin_amdgcn_rcpf(s);
 }
 
-// The FP64 path's two-chord bounds (bg_start) in FP32; the chords' constant
-// is c0, which FP32 could not form where its terms cancel.
+// The chord bounds of bg_start in FP32 (CHORDS chords); the chords'
+// constant is c0, which FP32 could not form where its terms cancel.
+template <int CHORDS>
 __device__ __forceinline__ float bg_start32(const Arrow1f& P) {
   float U = quad_zero32(P.gb, P.b1s + P.b2s, 1.0f);
   const float b2r = P.b2s * P.rab;
   const float c = P.c0;
 #pragma unroll
-  for (int j = 0; j < kChords; ++j) {
+  for (int j = 0; j < CHORDS; ++j) {
     const float k = b2r * __builtin_amdgcn_rcpf(U + P.ab);
     U = __builtin_fminf(U, quad_zero32(c, P.b1s, 1.0f + k));
   }
@@ -314,6 +328,7 @@ __device__ __forceinline__ double start_point(const Arrow1& P, double rab) {
 // Tangent-and-chord pairs of the two starts (mu, nu).
 constexpr int kStartPairsMu = 1;
 constexpr int kStartPairsNu = 2;
+
 
 // One Borges-Gragg step from x on either side of the zero (Sec. 1.4.1: the
 // iteration converges monotonically from any start in (0, inf)).  Sets stop
@@ -508,11 +523,16 @@ __device__ __forceinline__ void zeros_newton(const Arrow1& P1, const Arrow1& P2,
 }
 
 // ---------------------------------------------------------------------------
-// FP32 Borges-Gragg for the FP32-storage form: the same iteration in single
-// precision (v_rcp_f32 and v_sqrt_f32 are accurate to about one ulp).
+// FP32 Borges-Gragg for the unrefined FP32 form (an ablation): the same
+// iteration in single precision (v_rcp_f32 and v_sqrt_f32 are accurate to
+// about one ulp).
 // conv reports a stop by the precision test or at the zero.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop, bool& conv) {
+struct Move32 {
+  float xn, f, fp, w0m1;
+};
+
+__device__ __forceinline__ Move32 bg_move32(const Arrow1f& P, float x) {
   const float p = x + P.ab;
   const float rx = __builtin_amdgcn_rcpf(x);
   const float rp = __builtin_amdgcn_rcpf(p);
@@ -524,11 +544,6 @@ __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop
   // usual form has no such cancellation.
   const float f = x < P.ab ? ((x - P.c0) - q1) + q2 * (x * P.rab) : ((x - P.gb) - q1) - q2;
   const float fp = __builtin_fmaf(q1, rx, __builtin_fmaf(q2, rp, 1.0f));
-  if (f <= 0.0f) {
-    stop = true;
-    conv = true;
-    return x;
-  }
   const float w0m1 = (q2 * P.ab) * (rp * rp);
   const float w0 = w0m1 + 1.0f;
   const float a = -w0 * rx;
@@ -546,36 +561,57 @@ __device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop
     xn = sigma >= 0.0f ? (sigma + sq) * __builtin_amdgcn_rcpf(2.0f * w0)
                        : (2.0f * w1) * __builtin_amdgcn_rcpf(sq - sigma);
   }
-  if (!(xn < x)) {
+  return Move32{xn, f, fp, w0m1};
+}
+
+// One step of the iteration with its stop tests (the unrefined form).
+__device__ __forceinline__ float bg_step32(const Arrow1f& P, float x, bool& stop, bool& conv) {
+  const Move32 m = bg_move32(P, x);
+  if (m.f <= 0.0f || !(m.xn < x)) {
+    // at the zero, or rounding no longer moves x down
     stop = true;
     conv = true;
     return x;
   }
-  const float D = x - xn;
-  if (w0m1 * (D * D) * D <= 4.0f * kEps32 * (xn * xn) * (xn + P.ab) * fp) {
+  const float D = x - m.xn;
+  if (m.w0m1 * (D * D) * D <= 4.0f * kEps32 * (m.xn * m.xn) * (m.xn + P.ab) * m.fp) {
     stop = true;
     conv = true;
   }
-  return xn;
+  return m.xn;
 }
 
-// One FP64 Newton step on f from an FP32 zero (the iteration of Sec. 1.4.2
-// applied once, as a refinement).  bad reports a correction that is not
-// small (the FP32 zero was not close).
+// One step from an upper bound of the zero with no stop test, for the start
+// of the FP32-storage form's Newton step (which checks what it is given); a
+// step that does not give a positive iterate leaves x as it is.
+__device__ __forceinline__ float bg_once32(const Arrow1f& P, float x) {
+  const float xn = bg_move32(P, x).xn;
+  return xn > 0.0f ? xn : x;
+}
+
+// One FP64 Newton step on f from an FP32 estimate x of the zero (the
+// iteration of Sec. 1.4.2 applied once, as a refinement).  f is increasing
+// and concave with t |f''(t)| <= 2 f'(t), so from a start delta away from
+// the zero, on either side, the step lands left of it by at most about
+// delta^2 / x.  bad reports a correction above 2^-14 x (or a non-positive
+// iterate): below it the step leaves at most about 2^-28 x, and as the zero
+// is at most 2 ||A||, the eigenvalue it gives is off by at most
+// eps32 ||A|| / 16 before rounding.
 __device__ __forceinline__ double newton_refine(const Arrow1& P, double x, bool& bad) {
   const Spec s = spec_eval(P, x);
   const double dx = ddiv(s.f, s.fp);
   const double xn = x - dx;
-  bad = !(dabs(dx) <= 0x1p-12 * x) || !(xn > 0.0);
+  bad = !(dabs(dx) <= 0x1p-14 * x) || !(xn > 0.0);
   return xn;
 }
 
 // ---------------------------------------------------------------------------
 // The whole solve.  Input: the 6 unique entries (any doubles).  Output: lam
-// ascending, V[3r + c] = row r of eigenvector c.  F32R selects the FP32 zero
-// finder with FP64 refinement and an FP64 re-orthogonalisation; with
-// kFlagUnrefined the FP32 zeros are used as they are, with the paper's
-// vector formulas (zeros the FP32 finder cannot give still go to FP64 BG).
+// ascending, V[3r + c] = row r of eigenvector c.  kFormF32R takes an FP32
+// estimate of each zero, one FP64 Newton step and an FP64
+// re-orthogonalisation; kFormF32 uses the zeros of an FP32 Borges-Gragg
+// iteration as they are, with the paper's vector formulas (zeros the FP32
+// finder cannot give still go to FP64 BG).
 // Returns branch | it_mu << 8 | it_nu << 16.  bad is set for a matrix with
 // a NaN or infinite entry: its outputs are then meaningless (the solve runs
 // on the non-finite values, every loop bounded) and the caller stores NaN in
@@ -600,7 +636,7 @@ __device__ __forceinline__ Vec3 axpy(double s, const Vec3& a, const Vec3& b) {
               __builtin_fma(s, a.z, b.z)};
 }
 
-template <bool VECS, bool F32R>
+template <bool VECS, int FORM>
 __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
                                       double (&lam)[3], double (&V)[9], bool& bad) {
   double a11 = ain[0], a12 = ain[1], a13 = ain[2], a22 = ain[3], a23 = ain[4],
@@ -725,7 +761,53 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
     const Arrow1 P1{b1s, b2s, al, ga - al1};
     const Arrow1 P2{b2s, b1s, al, al2 - ga};
     double mu = 0.0, nu = 0.0;
-    if (F32R) {
+    if (FORM == kFormF32R) {
+      // FP32 storage with FP64 refinement: in FP32, the three-chord upper
+      // bound of the zero and one Borges-Gragg step from it; then one FP64
+      // Newton step (Sec. 1.4.2), which squares the relative error.
+      const double rab = rcp1(P1.ab);  // both problems share abar
+      const Arrow1f Q1{(float)P1.b1s, (float)P1.b2s, (float)P1.ab, (float)P1.gb,
+                       (float)__builtin_fma(P1.b2s, rab, P1.gb), (float)rab};
+      const Arrow1f Q2{(float)P2.b1s, (float)P2.b2s, (float)P2.ab, (float)P2.gb,
+                       (float)__builtin_fma(P2.b2s, rab, P2.gb), (float)rab};
+      const float y1 = bg_once32(Q1, bg_start32<kChordsRefine>(Q1));
+      const float y2 = bg_once32(Q2, bg_start32<kChordsRefine>(Q2));
+      double x1 = (double)y1, x2 = (double)y2;
+      // the FP32 problem must be representable away from the poles
+      if (!(Q1.b1s >= 0x1p-100f && Q1.b2s >= 0x1p-100f && Q1.ab >= 0x1p-60f &&
+            y1 > 0x1p-100f && y2 > 0x1p-100f)) {
+        // no usable FP32 start: the FP64 bounds of bg_start, too far for
+        // the Newton step, whose check then hands them to FP64 Borges-Gragg
+        // (a branch of its own, which the empty asm keeps from being
+        // evaluated on every lane)
+        asm volatile("");
+        x1 = bg_start(P1, rab);
+        x2 = bg_start(P2, rab);
+      }
+      bool bad1, bad2;
+      mu = newton_refine(P1, x1, bad1);
+      nu = newton_refine(P2, x2, bad2);
+      it1 = it2 = 2;  // one FP32 and one FP64 evaluation of f per root
+      if (flags & kFlagRefineConverge) bad1 = bad2 = true;
+      if (bad1 || bad2) {
+        // The start was too far for one Newton step (a zero FP32 does not
+        // resolve, or an arrow outside FP32's range), or every root
+        // converges (kFlagRefineConverge): continue with FP64 Borges-Gragg
+        // steps.  f is concave, so the Newton iterate lies left of the zero
+        // when the start is right of it; when it is not positive the start
+        // is taken instead.
+        if (bad1 && !(mu > 0.0)) mu = x1;
+        if (bad2 && !(nu > 0.0)) nu = x2;
+        bool s1 = !bad1, s2 = !bad2;
+        for (int k = 0; k < kMaxIter; ++k) {
+          if (s1 && s2) break;
+          if (!s1) { ++it1; mu = bg_step(P1, mu, s1); }
+          if (!s2) { ++it2; nu = bg_step(P2, nu, s2); }
+        }
+      }
+    } else if (FORM == kFormF32) {
+      // The unrefined FP32 ablation: Borges-Gragg in FP32 from the FP32
+      // two-chord start, its zeros used as they are.
       const double rab = rcp1(P1.ab);  // both problems share abar
       const Arrow1f Q1{(float)P1.b1s, (float)P1.b2s, (float)P1.ab, (float)P1.gb,
                        (float)__builtin_fma(P1.b2s, rab, P1.gb), (float)rab};
@@ -733,7 +815,7 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
                        (float)__builtin_fma(P2.b2s, rab, P2.gb), (float)rab};
       // the FP32 problem must be representable away from the poles
       bool fb = !(Q1.b1s >= 0x1p-100f && Q1.b2s >= 0x1p-100f && Q1.ab >= 0x1p-60f);
-      float y1 = bg_start32(Q1), y2 = bg_start32(Q2);
+      float y1 = bg_start32<kChords>(Q1), y2 = bg_start32<kChords>(Q2);
       bool s1 = false, s2 = false, c1 = false, c2 = false;
       for (int k = 0; k < kMaxIter32; ++k) {
         if (s1 && s2) break;
@@ -741,37 +823,15 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
         if (!s2) { ++it2; y2 = bg_step32(Q2, y2, s2, c2); }
       }
       fb = fb || !c1 || !c2 || !(y1 > 0x1p-100f) || !(y2 > 0x1p-100f);
-      bool bad1 = false, bad2 = false;
-      if (!fb) {
-        if (flags & kFlagUnrefined) {
-          mu = (double)y1;
-          nu = (double)y2;
-        } else {
-          mu = newton_refine(P1, (double)y1, bad1);
-          nu = newton_refine(P2, (double)y2, bad2);
-          if (flags & kFlagRefineConverge) bad1 = bad2 = true;
-        }
-      }
       if (fb) {
         // no usable FP32 zero: the FP64 zero finder from its own start
         int j1, j2;
         zeros_bg(P1, P2, mu, nu, j1, j2);
         it1 += j1;
         it2 += j2;
-      } else if (bad1 || bad2) {
-        // The FP32 zero was too far off for one Newton step (rare: a zero
-        // the FP32 arithmetic does not resolve), or every root converges
-        // (kFlagRefineConverge): continue with FP64 Borges-Gragg steps.  f
-        // is concave, so the Newton iterate lies left of the zero; when it
-        // is not positive the FP32 zero was right of it.
-        if (bad1 && !(mu > 0.0)) mu = (double)y1;
-        if (bad2 && !(nu > 0.0)) nu = (double)y2;
-        bool s1 = !bad1, s2 = !bad2;
-        for (int k = 0; k < kMaxIter; ++k) {
-          if (s1 && s2) break;
-          if (!s1) { ++it1; mu = bg_step(P1, mu, s1); }
-          if (!s2) { ++it2; nu = bg_step(P2, nu, s2); }
-        }
+      } else {
+        mu = (double)y1;
+        nu = (double)y2;
       }
     } else if (flags & kFlagNewton) {
       zeros_newton(P1, P2, mu, nu, it1, it2);
@@ -788,7 +848,7 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
       const double mua = mu + al, nua = nu + al;
       const Vec3 u1{be1 * mua, be2 * mu, mu * mua};
       const Vec3 u3{be1 * nu, be2 * nua, -nu * nua};
-      if (F32R && !(flags & kFlagUnrefined)) {
+      if (FORM == kFormF32R) {
         // one Gram-Schmidt re-orthogonalisation of u3 against the unit u1,
         // before u3 is normalised
         v2 = normalized(u1);
@@ -797,7 +857,7 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
         v2 = normalized(u1);
         v0 = normalized(u3);
       }
-      if (F32R && (flags & kFlagUnrefined)) {
+      if (FORM == kFormF32) {
         // the ablation keeps the paper's formula for u2
         const Vec3 u2{-be2 * mu * nua, be1 * nu * mua, be1 * be2 * al};
         v1 = normalized(u2);
