@@ -137,11 +137,13 @@ struct Rot2 {
 __device__ __forceinline__ Rot2 rot2(double p, double r, double q) {
   const double d = 0.5 * (q - p);
   const double ad = dabs(d);
-  double u = 0.0;
-  if (__builtin_fmax(ad, dabs(r)) >= 0x1p-500) {
-    const double rr = sqrt2(__builtin_fma(d, d, r * r));
-    u = ddiv(r, ad + rr);
-  }
+  // 2^-1000 under the root keeps it normal and the quotient's divisor at
+  // least 2^-500 (d = r = 0 gives u = 0, and r = 0 gives u = 0 exactly), at
+  // no cost in the FMA chain; it moves hypot(d, r) by under half an ulp
+  // unless d^2 + r^2 < 2^-946, where the block is below 2^-470 of a matrix
+  // scaled to max |a_ij| >= 1/2.
+  const double rr = sqrt2(__builtin_fma(d, d, __builtin_fma(r, r, 0x1p-1000)));
+  const double u = ddiv(r, ad + rr);
   const double c = rsqrt2(__builtin_fma(u, u, 1.0));
   const double s = u * c;
   const bool keep = p >= q;
@@ -687,22 +689,22 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
   } else {
     diag = !(hh > tol_h * tol_h);
   }
-  const double rh = rsqrt2(hh);  // unused (inf/NaN) on diagonal lanes
-  const double h = hh * rh;
-  const double cg = be2 * rh;  // G = [[cg, -sg, 0], [sg, cg, 0], [0, 0, 1]]
-  const double sg = be1 * rh;
   const double al = al1 - al2;
-  // The test's right-hand side needs d1 and d2 only to a few ulps of the
-  // larger alpha: alpha1 - alpha s^2 and alpha2 + alpha s^2 serve.  The
-  // deflated branch forms them exactly (below).
-  const double s2 = sg * sg;
-  const double ee = al * sg * cg;
+  // The test |e| <= eps (|d1| + |d2|) on G A G^T, whose off-diagonal entry
+  // is e = alpha sg cg and whose diagonal is d1 = alpha1 cg^2 + alpha2 sg^2,
+  // d2 = alpha1 sg^2 + alpha2 cg^2 (sg = beta1/h, cg = beta2/h), taken
+  // times h^2: |alpha beta1 beta2| <= eps (|alpha1 beta2^2 + alpha2 beta1^2|
+  // + |alpha1 beta1^2 + alpha2 beta2^2|).  It needs no root or quotient, so
+  // G itself is formed only on lanes that deflate.  The exact beta- and
+  // combo-deflations (beta1, beta2 or alpha zero) make the left side zero.
+  const double b1s = be1 * be1, b2s = be2 * be2;
+  const double ee = al * be1 * be2;
   double rhs;
   if (flags & kFlagSimplified) {
     asm volatile("");
-    rhs = dabs(al1 + al2);
+    rhs = dabs(al1 + al2) * hh;
   } else {
-    rhs = dabs(__builtin_fma(-al, s2, al1)) + dabs(__builtin_fma(al, s2, al2));
+    rhs = dabs(__builtin_fma(al1, b2s, al2 * b1s)) + dabs(__builtin_fma(al1, b1s, al2 * b2s));
   }
   const bool defl = !diag && dabs(ee) <= kEps64 * rhs;
 
@@ -716,10 +718,14 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
     if (defl) {
       // accept d1 with G^T e1 = (cg, -sg, 0); solve [[d2, h], [h, gamma]]
       branch = kDeflated;
+      const double rh = rsqrt2(hh);
+      const double h = hh * rh;
+      const double cg = be2 * rh;  // G = [[cg, -sg, 0], [sg, cg, 0], [0, 0, 1]]
+      const double sg = be1 * rh;
       // d1, d2 with the smaller correction: bitwise exact for the beta- and
       // combo-deflations (sg or cg zero, or alpha zero)
       const bool small_s = dabs(sg) <= dabs(cg);
-      const double c2 = cg * cg;
+      const double s2 = sg * sg, c2 = cg * cg;
       const double d1 = small_s ? __builtin_fma(-al, s2, al1) : __builtin_fma(al, c2, al2);
       const double d2 = small_s ? __builtin_fma(al, s2, al2) : __builtin_fma(-al, c2, al1);
       const Rot2 T = rot2(d2, h, ga);
@@ -757,7 +763,6 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
   } else {
     branch = kReduced;
     // mu: rightmost zero of A - alpha1 I; nu: of P(alpha2 I - A)P
-    const double b1s = be1 * be1, b2s = be2 * be2;
     const Arrow1 P1{b1s, b2s, al, ga - al1};
     const Arrow1 P2{b2s, b1s, al, al2 - ga};
     double mu = 0.0, nu = 0.0;
