@@ -343,7 +343,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "kernel": "k_syev3_soa32<double, vecs>",
+                     "kernel": "k_syev3_soa32<0, true, false> (FP64 form, vectors)",
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "ms_per_launch": ms_launch,
                      "ms_per_launch_median": sorted(per_ms)[len(per_ms) // 2],
