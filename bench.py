@@ -421,20 +421,6 @@ def main():
         A, _ = gen.wide_range(1 << 28, seed=4, device=dev)
         run_variant("wide_range_256m_f64_soa", A, "soa", True, "f64", steps=5)
         run_variant("wide_range_256m_f64_soa_valsonly", A, "soa", False, "f64", steps=5)
-        # the same input in a (6, ld) buffer whose plane stride is the
-        # binding's output stride (n + 4160 here): no plane a multiple of
-        # 1 GiB from another
-        nn = A.shape[1]
-        ld = s3.out_stride(nn, 8)
-        Ab = torch.empty((6, ld), dtype=torch.float64, device=dev)
-        Ab[:, :nn].copy_(A)
-        del A
-        torch.cuda.empty_cache()
-        run_variant("wide_range_256m_f64_soa_staggered", Ab[:, :nn], "soa", True, "f64",
-                    steps=5)
-        del Ab
-        torch.cuda.empty_cache()
-        A, _ = gen.wide_range(1 << 28, seed=4, device=dev)
         Aa = A.t().contiguous()
         del A
         torch.cuda.empty_cache()
@@ -442,9 +428,8 @@ def main():
         del Aa
         torch.cuda.empty_cache()
         aos_ms = side["wide_range_256m_f64_aos"].get("ms_per_launch")
-        for k in ("wide_range_256m_f64_soa", "wide_range_256m_f64_soa_staggered"):
-            ms = side[k].get("ms_per_launch")
-            side[k + "_over_aos_time"] = ms / aos_ms if ms and aos_ms else None
+        ms = side["wide_range_256m_f64_soa"].get("ms_per_launch")
+        side["wide_range_256m_f64_soa_over_aos_time"] = ms / aos_ms if ms and aos_ms else None
         line["variants"] = side
         try:
             line["f32r_error_vs_fp64_oracle"] = f32r_errors(torch, gen, s3)

@@ -157,15 +157,15 @@ int batched_syev3_ex(int64_t n, const void* A, int64_t ld, int layout,
  * stride is >= n (0 means n).  The arithmetic is that of batched_syev3_ex,
  * so the results are bitwise the same for any strides.
  *
- * Why separate strides: the 18 planes of an SoA solve are streamed together,
- * each wavefront touching all of them at the same element offset.  When the
- * plane stride is a multiple of 1 GiB (n = 2^28 FP64 matrices: planes
- * exactly 2 GiB apart), the planes' streams can fall on the same HBM
- * channels at once, depending on where the allocations land; on an MI355X
- * such a 2^28-matrix FP64 solve took 8.3 ms with every stride n and 6.6 ms
- * with the strides 32.5 KiB longer.  A caller that cannot choose the layout
- * of its input can still give the outputs a stride of their own (the Python
- * binding does for strides within 32.5 KiB of a multiple of 1 GiB).
+ * Separate strides let a caller solve planes that live in buffers of their
+ * own (rows of wider arrays, outputs written into a larger result set)
+ * without copies.  Performance note: the 18 planes are streamed together,
+ * each wavefront touching all of them at the same element offset, so how
+ * fast a very large batch runs depends on which HBM channels the planes'
+ * physical pages share.  On an MI355X a 2^28-matrix FP64 solve took 6.2 to
+ * 8.3 ms from one allocation to the next (the AoS layout, three streams,
+ * 6.4 to 6.9 ms); within one allocation, strides 32.5 KiB longer than n
+ * were as fast or up to 7% slower.
  * Arrays whose plane ranges interleave are refused (SYEV3_E_ALIAS) even
  * when their planes do not overlap.  Errors as batched_syev3_ex.
  */

@@ -22,7 +22,7 @@ from ._lib import (AOS, AOS9, F32, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD
                    Syev3Error)
 
 __all__ = ["syev3", "syev3_inplace", "batched_syev3", "batched_syev3_ex", "batched_syev3_info",
-           "batched_syev3_strided", "out_stride",
+           "batched_syev3_strided",
            "F64", "F32_REFINE", "F32", "SOA", "AOS", "AOS9", "FLAG_SIMPLIFIED_DEFLATION",
            "FLAG_NO_H_GUARD", "FLAG_NEWTON", "FLAG_PAPER_BG", "FLAG_REFINE_CONVERGE", "FLAG_NO_SCALE",
            "Syev3Error",
@@ -66,32 +66,6 @@ def batched_syev3_strided(n, A_ptr, lda, lam_ptr, ldl, V_ptr, ldv, dtype, flags,
                           stream_handle) -> int:
     return _lib.lib().batched_syev3_strided(n, A_ptr, lda, lam_ptr, ldl, V_ptr, ldv, dtype,
                                             flags, stream_handle)
-
-
-# Plane stride of the outputs the binding allocates for SoA solves.  The 12
-# output planes and the 6 input planes are streamed together, each wavefront
-# at the same element offset in every plane.  Planes a multiple of 1 GiB
-# apart (2^27 and 2^28 FP64 matrices) can then meet on the same HBM
-# channels: on an MI355X a 2^28-matrix FP64 solve took 8.3 ms with every
-# stride n and 6.6 ms with the strides offset by 32.5 KiB, depending on
-# where the allocations landed (other runs of the plain layout took 6.5 ms).
-# At 2^26 matrices (planes 512 MiB apart) the same offset made the solve 4%
-# slower, so it is applied only to strides within 32.5 KiB of a multiple of
-# 1 GiB: such a stride is lengthened to 32.5 KiB past the multiple.
-_GIB = 1 << 30
-_STAGGER_BYTES = 33280
-
-
-def out_stride(n: int, esize: int) -> int:
-    """Plane stride (elements) of the SoA outputs syev3() allocates: n,
-    unless n * esize lies within 32.5 KiB of a multiple of 1 GiB (and is at
-    least 1 GiB); then the next stride whose byte length is 32.5 KiB past
-    that multiple."""
-    s = n * esize
-    r = s % _GIB
-    if s < _GIB or _STAGGER_BYTES <= r <= _GIB - _STAGGER_BYTES:
-        return n
-    return n + ((_STAGGER_BYTES - r) % _GIB) // esize
 
 
 def _dtype_code(t: torch.Tensor, refine: bool = True) -> int:
@@ -157,8 +131,8 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
     layout "soa": A has shape (6, n), rows a11 a12 a13 a22 a23 a33, row
     stride ld >= n (a slice of a (6, ld) buffer is fine).  Returns lam (3, n)
     and V (9, n) with V[3*r + c, i] = row r of eigenvector c of matrix i,
-    rows of one buffer whose row stride is out_stride(n, element size)
-    (n, except next to multiples of 1 GiB per plane).
+    rows of one contiguous (12, n) buffer (with info=True, of one (12, ld)
+    buffer: the kernel then takes the input's stride for every array).
     layout "aos": A has shape (n, 6), contiguous.  Returns lam (n, 3) and
     V (n, 3, 3) with columns the eigenvectors (as torch.linalg.eigh).
     layout "aos9": A holds full matrices, (n, 3, 3) or (n, 9), contiguous
@@ -178,7 +152,7 @@ def syev3(A: torch.Tensor, *, vectors: bool = True, layout: str = "soa",
         if out is None:
             # one buffer of 3 (+ 9) planes; with info the kernel takes one
             # stride for every array, the input's
-            ldo = ld if info else out_stride(n, A.element_size())
+            ldo = ld if info else n
             buf = torch.empty((12 if vectors else 3, max(ldo, 1)), dtype=A.dtype,
                               device=A.device)
             lam, V = buf[:3, :n], (buf[3:12, :n] if vectors else None)

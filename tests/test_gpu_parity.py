@@ -642,15 +642,14 @@ def test_explicit_stream_and_fp32_plane_stride():
     W[:, :n] = A[:, :n].float()
     lam_s, V_s = solve_soa(W[:, :n])
     lam_c, V_c = solve_soa(W[:, :n].contiguous())
-    assert lam_s.stride(0) == s3.out_stride(n, 4)
+    assert lam_s.stride(0) == n
     assert torch.equal(lam_s, lam_c) and torch.equal(V_s, V_c)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_a_stride_per_array(dtype):
     """batched_syev3_strided: input, eigenvalues and vectors each with a
-    plane stride of its own (including the binding's staggered output
-    buffer) give the bits of the one-stride call; the results meet the
+    plane stride of its own give the bits of the one-stride call; the results meet the
     oracle's bars; arrays whose plane ranges interleave are refused."""
     import ctypes
     n = 70_001
@@ -671,7 +670,7 @@ def test_a_stride_per_array(dtype):
         assert torch.equal(lb[:, :n], lam_ref) and torch.equal(vb[:, :n], V_ref)
         # the gaps between planes are not written
         assert torch.isnan(lb[:, n:]).all() and torch.isnan(vb[:, n:]).all()
-    # the binding's default: one staggered buffer for lam and V
+    # the binding's default: one contiguous buffer for lam and V
     lam, V = s3.syev3(A)
     torch.cuda.synchronize()
     assert torch.equal(lam, lam_ref) and torch.equal(V, V_ref)
@@ -682,22 +681,6 @@ def test_a_stride_per_array(dtype):
                                   ctypes.c_void_p(buf.data_ptr()), 4 * n,
                                   ctypes.c_void_p(buf[1].data_ptr()), n, dt, 0, sh)
     assert rc == -5
-
-
-def test_binding_staggers_outputs_at_1_gib_planes():
-    """With planes of exactly 1 GiB (2^27 FP64 matrices) the binding lays
-    the outputs out with a plane stride of n plus 32.5 KiB; the results
-    are those of contiguous outputs."""
-    n = 1 << 27
-    A = gen.normal(n, 64, "cuda")
-    lam, _ = s3.syev3(A, vectors=False)
-    assert lam.stride(0) == n + 4160
-    lam_c = torch.empty((3, n), dtype=torch.float64, device="cuda")
-    s3.syev3(A, vectors=False, out=(lam_c, None))
-    torch.cuda.synchronize()
-    assert torch.equal(lam, lam_c)
-    del A, lam, lam_c
-    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
