@@ -592,18 +592,27 @@ __device__ __forceinline__ float bg_once32(const Arrow1f& P, float x) {
 }
 
 // One FP64 Newton step on f from an FP32 estimate x of the zero (the
-// iteration of Sec. 1.4.2 applied once, as a refinement).  f is increasing
-// and concave with t |f''(t)| <= 2 f'(t), so from a start delta away from
-// the zero, on either side, the step lands left of it by at most about
-// delta^2 / x.  bad reports a correction above 2^-14 x (or a non-positive
-// iterate): below it the step leaves at most about 2^-28 x, and as the zero
-// is at most 2 ||A||, the eigenvalue it gives is off by at most
-// eps32 ||A|| / 16 before rounding.
-__device__ __forceinline__ double newton_refine(const Arrow1& P, double x, bool& bad) {
+// iteration of Sec. 1.4.2, as a refinement).  f is increasing and concave
+// with t |f''(t)| <= 2 f'(t), so from a start delta away from the zero, on
+// either side, the step lands left of it by at most about delta^2 / x.
+//  * bad: a correction above 2^-14 x (or a non-positive iterate); the lane
+//    then goes on with FP64 Borges-Gragg steps.  Below it the step leaves
+//    at most about 2^-28 x: as the zero is at most 2 ||A||, an eigenvalue
+//    off by at most eps32 ||A|| / 16 before rounding.
+//  * again: a correction above 2^-22 x; one more step then leaves at most
+//    about 2^-56 x.  An eigenvalue formed as a difference (alpha2 - nu, say)
+//    can be far smaller than the zero, and its relative error is the
+//    zero's error over it: on SPD matrices of condition 1e8, a CPU
+//    emulation of this arithmetic puts the smallest eigenvalue's worst
+//    relative error at 3e-3 after one step and 1e-6 with the second step
+//    where the first moved more than 2^-22 x.
+__device__ __forceinline__ double newton_refine(const Arrow1& P, double x, bool& bad,
+                                                bool& again) {
   const Spec s = spec_eval(P, x);
   const double dx = ddiv(s.f, s.fp);
   const double xn = x - dx;
   bad = !(dabs(dx) <= 0x1p-14 * x) || !(xn > 0.0);
+  again = !(dabs(dx) <= 0x1p-22 * x);
   return xn;
 }
 
@@ -768,8 +777,9 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
     double mu = 0.0, nu = 0.0;
     if (FORM == kFormF32R) {
       // FP32 storage with FP64 refinement: in FP32, the three-chord upper
-      // bound of the zero and one Borges-Gragg step from it; then one FP64
-      // Newton step (Sec. 1.4.2), which squares the relative error.
+      // bound of the zero and one Borges-Gragg step from it; then an FP64
+      // Newton step (Sec. 1.4.2), which squares the relative error, and a
+      // second one where the first moved the zero by more than 2^-22.
       const double rab = rcp1(P1.ab);  // both problems share abar
       const Arrow1f Q1{(float)P1.b1s, (float)P1.b2s, (float)P1.ab, (float)P1.gb,
                        (float)__builtin_fma(P1.b2s, rab, P1.gb), (float)rab};
@@ -789,11 +799,26 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
         x1 = bg_start(P1, rab);
         x2 = bg_start(P2, rab);
       }
-      bool bad1, bad2;
-      mu = newton_refine(P1, x1, bad1);
-      nu = newton_refine(P2, x2, bad2);
+      bool bad1, bad2, again1, again2, unused;
+      mu = newton_refine(P1, x1, bad1, again1);
+      nu = newton_refine(P2, x2, bad2, again2);
       it1 = it2 = 2;  // one FP32 and one FP64 evaluation of f per root
       if (flags & kFlagRefineConverge) bad1 = bad2 = true;
+      // the second Newton step, per root, where the first moved the zero by
+      // more than 2^-22 of it (and the lane is not going on to Borges-Gragg);
+      // branches of their own (the empty asm keeps the compiler from
+      // evaluating them on every lane), skipped by wavefronts none of whose
+      // lanes need them
+      if (again1 && !bad1) {
+        asm volatile("");
+        ++it1;
+        mu = newton_refine(P1, mu, unused, unused);
+      }
+      if (again2 && !bad2) {
+        asm volatile("");
+        ++it2;
+        nu = newton_refine(P2, nu, unused, unused);
+      }
       if (bad1 || bad2) {
         // The start was too far for one Newton step (a zero FP32 does not
         // resolve, or an arrow outside FP32's range), or every root

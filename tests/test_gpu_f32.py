@@ -4,10 +4,11 @@ the same inputs: the FP32 values, widened exactly.
 Bars, in units of eps32 = 2^-23 (u = eps32 / 2 is the FP32 rounding unit):
 
 F32_REFINE.  The arrow, the deflation test and the vectors are FP64; an
-FP32 estimate of each zero gets one FP64 Newton step (Sec. 1.4.2).  f is
-increasing and concave with t |f''| <= 2 f', so the step leaves at most
-about (correction)^2 / zero; a correction above 2^-14 of the zero sends the
-lane to the FP64 zero finder, so what the step leaves is at most 2^-28 of a
+FP32 estimate of each zero gets an FP64 Newton step (Sec. 1.4.2), and a
+second one where the first moved it by more than 2^-22.  f is increasing and
+concave with t |f''| <= 2 f', so a step leaves at most about
+(correction)^2 / zero; a correction above 2^-14 of the zero sends the lane
+to the FP64 zero finder, so what the steps leave is at most 2^-28 of a
 zero <= 2 ||A||_F, i.e. eps32 ||A||_F / 16.  What remains is the rounding of
 the outputs to FP32: |dlambda_i| <= u |lambda_i| <= u ||A||_F,
 ||dV||_F <= u sqrt(3).
@@ -116,13 +117,14 @@ def test_unrefined_fp32_ablation(kind, n, seed):
     ("pow2_range", 100_003, 43),
 ])
 def test_refine_to_convergence(kind, n, seed):
-    """FLAG_REFINE_CONVERGE continues every root after the Newton step with
-    FP64 Borges-Gragg steps from the Newton iterate: the path the default
-    takes only for a root whose Newton correction exceeds 2^-14 of it.
-    Without the flag a root takes exactly two evaluations of f (one FP32,
-    one FP64) unless it took that path; every such root takes at least one
-    evaluation more with the flag, no root takes fewer, and the results meet
-    the refined form's bars against the oracle."""
+    """FLAG_REFINE_CONVERGE continues every root after the first Newton
+    step with FP64 Borges-Gragg steps from the Newton iterate: the path the
+    default takes only for a root whose Newton correction exceeds 2^-14 of
+    it.  Without the flag a root takes two or three evaluations of f (one
+    FP32, one or two FP64 Newton steps) unless it took that path; with it
+    every root takes at least one Borges-Gragg step (three evaluations or
+    more), no root takes fewer than without it, and the results meet the
+    refined form's bars against the oracle."""
     A32 = _inputs(kind, n, seed)
     lam, eerr, res, orth = _measure(A32, refine=True, flags=s3.FLAG_REFINE_CONVERGE)
     print(f"F32_REFINE converge {kind} n={n} max |dlam|/(eps32|A|) {eerr.max():.3f} "
@@ -139,10 +141,9 @@ def test_refine_to_convergence(kind, n, seed):
     assert np.array_equal(i0 & 0xFF, i1 & 0xFF) and red.sum() > n // 2
     for shift in (8, 16):
         e0, e1 = (i0[red] >> shift) & 0xFF, (i1[red] >> shift) & 0xFF
-        newton_only = e0 == 2
-        print(f"  roots finished by the Newton step: {newton_only.mean():.4f}", flush=True)
-        assert np.all(e0 >= 2) and np.all(e1 >= e0)
-        assert np.all(e1[newton_only] > 2)
+        newton_only = e0 <= 3
+        print(f"  roots finished by Newton steps: {newton_only.mean():.4f}", flush=True)
+        assert np.all(e0 >= 2) and np.all(e1 >= 3) and np.all(e1 >= e0)
         assert newton_only.mean() > (0.95 if kind == "stress_mix" else 0.99)
 
 
