@@ -384,7 +384,9 @@ def main():
             torch.cuda.synchronize()
             fn = (lambda: s3.syev3(A, layout=layout, vectors=vectors, out=out, refine=refine,
                                    flags=flags))
-            _, per, span = timed_launches(fn, steps, 5, torch)  # 5 warm-up launches
+            # the headline's warm-up: the chip's clock settles over the first
+            # launches after a change of load
+            _, per, span = timed_launches(fn, steps, args.warmup, torch)
             msl = sum(per) / len(per)
             b = BYTES_PER_MATRIX[(dtype_key, vectors)] * nn
             del out
