@@ -267,7 +267,7 @@ typedef struct {
   int32_t max_segments_per_tick; /* requests per tick,
                                     1 .. SYEV3_SERVER_MAX_SEGMENTS */
   int32_t grid_blocks;         /* blocks of the persistent kernel, at most
-                                  2^24; 0 = auto (8 per compute unit) */
+                                  2^24; 0 = auto (32 per compute unit) */
   int32_t use_graphs;          /* 1: launch ticks through captured graphs */
 } syev3_server_opts;
 

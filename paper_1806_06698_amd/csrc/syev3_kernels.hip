@@ -361,33 +361,44 @@ hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout,
 // binary search of the (small) table, so each wavefront runs one dtype and
 // one code path.  Per-matrix arithmetic is exactly the batched kernels'.
 // ---------------------------------------------------------------------------
+// One tile of segment s: matrices t0 .. t0 + kBlock - 1.  The tile's first
+// matrix is folded into the plane bases (uniform, in scalar registers), so
+// each lane adds only threadIdx.x elements as a 32-bit byte offset, whatever
+// the request's size; the stores again see it as 32-bit past the solve (the
+// empty asm re-defines it), so no 64-bit address is formed per access, as in
+// the batched SoA kernel.  Every tile solves for vectors, and a request
+// without them (V null, a uniform branch) skips only their stores: with one
+// solve per form the kernel holds two inlined solves, not four, and fits in
+// 60 VGPRs (8 waves per SIMD; four solves needed 84, 5 waves).
 template <int FORM>
-__device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t i) {
+__device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t t0) {
   using T = Storage<FORM>;
-  const T* A = (const T*)s.A;
-  T* lam = (T*)s.lambda;
-  T* V = (T*)s.V;
-  const int64_t lda = s.lda, ld = s.n;
+  const int64_t pa = s.lda * (int64_t)sizeof(T), po = s.n * (int64_t)sizeof(T);
+  const char* A = (const char*)s.A + t0 * (int64_t)sizeof(T);
+  char* L = (char*)s.lambda + t0 * (int64_t)sizeof(T);
+  char* W = (char*)s.V + t0 * (int64_t)sizeof(T);
+  const bool vecs = s.V != nullptr;
+  const uint32_t off = threadIdx.x * (uint32_t)sizeof(T);
   double a[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream(A + k * lda + i);
+  for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream((const T*)(A + k * pa + off));
   double l[3], v[9];
   bool bad;
-  if (V) {
-    solve3<true, FORM>(a, s.flags, l, v, bad);
+  solve3<true, FORM>(a, s.flags, l, v, bad);
+  uint32_t soff = off;
+  asm volatile("" : "+v"(soff));
 #pragma unroll
-    for (int k = 0; k < 9; ++k) st_stream((T)v[k], V + k * ld + i);
-  } else {
-    solve3<false, FORM>(a, s.flags, l, v, bad);
+  for (int j = 0; j < 3; ++j) st_stream((T)l[j], (T*)(L + j * po + soff));
+  if (vecs) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) st_stream((T)v[k], (T*)(W + k * po + soff));
   }
-#pragma unroll
-  for (int j = 0; j < 3; ++j) st_stream((T)l[j], lam + j * ld + i);
   if (bad) {  // a NaN or infinite entry: NaN in every output of the matrix
 #pragma unroll
-    for (int j = 0; j < 3; ++j) st_stream(qnan<T>(), lam + j * ld + i);
-    if (V) {
+    for (int j = 0; j < 3; ++j) st_stream(qnan<T>(), (T*)(L + j * po + soff));
+    if (vecs) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) st_stream(qnan<T>(), V + k * ld + i);
+      for (int k = 0; k < 9; ++k) st_stream(qnan<T>(), (T*)(W + k * po + soff));
     }
   }
 }
@@ -403,11 +414,11 @@ __global__ __launch_bounds__(kBlock) void k_syev3_segments(const TickTable* __re
       if (t->seg[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
     }
     const Segment s = t->seg[lo];
-    const int64_t i = (tile - s.tile_begin) * kBlock + threadIdx.x;
-    if (i < s.n) {
+    const int64_t t0 = (tile - s.tile_begin) * kBlock;  // the tile's first matrix
+    if (t0 + threadIdx.x < s.n) {
       // the server admits the FP64 and the refined FP32 form
-      if (s.dtype == kFormF64) solve_segment_tile<kFormF64>(s, i);
-      else solve_segment_tile<kFormF32R>(s, i);
+      if (s.dtype == kFormF64) solve_segment_tile<kFormF64>(s, t0);
+      else solve_segment_tile<kFormF32R>(s, t0);
     }
   }
 }

@@ -321,7 +321,11 @@ int syev3_server::init(const syev3_server_opts& opts) {
   for (int k = o.max_requests - 1; k >= 0; --k) free_slots.push_back(k);
   done_ids.reserve(o.max_requests);
   table_bytes = syev3::tick_table_bytes(o.max_segments_per_tick);
-  grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : syev3::device_cu_count() * 8;
+  // 32 workgroups per compute unit by default: on the stress-mix serving
+  // load (input views, 256 requests in flight) this served 3-10% more
+  // matrices per second than 8 per unit, with lower latency at 80% of
+  // saturation and the same at 2000 requests/s.
+  grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : syev3::device_cu_count() * 32;
   ticks.resize(o.max_inflight_ticks);
   for (auto& tk : ticks) {
     tk.reqs.reserve(o.max_segments_per_tick);
