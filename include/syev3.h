@@ -70,13 +70,20 @@ extern "C" {
 /* dtypes */
 #define SYEV3_F64 0          /* FP64 storage, FP64 arithmetic */
 #define SYEV3_F32_REFINE 1   /* FP32 storage; FP64 reduction, deflation test
-                                and eigenvectors, FP32 zero finder followed
-                                by one FP64 Newton step per root */
-#define SYEV3_F32 2          /* as SYEV3_F32_REFINE without the refinement:
-                                the FP32 zeros are used unrefined and the
-                                vectors come from the formulas of Sec. 1
-                                without re-orthogonalisation.  For measuring
-                                what the refinement buys (an ablation); the
+                                and eigenvectors.  Each root: an FP32 start
+                                and one FP32 Borges-Gragg step, then an FP64
+                                Newton step (Sec. 1.4.2), a second one where
+                                the first moved it by more than 2^-22 of
+                                itself, and FP64 Borges-Gragg steps where it
+                                moved it by more than 2^-14.  Eigenvalues
+                                within eps32 ||A|| / 16 of the exact ones
+                                before rounding to FP32 */
+#define SYEV3_F32 2          /* FP32 storage without the refinement: the
+                                zeros of an FP32 Borges-Gragg iteration are
+                                used as they are and the vectors come from
+                                the formulas of Sec. 1 without
+                                re-orthogonalisation.  For measuring what
+                                the refinement buys (an ablation); the
                                 server does not accept it */
 
 /* layouts */
@@ -101,12 +108,12 @@ extern "C" {
                                      For measuring what the default start
                                      and stop test save; SYEV3_F64 only, not
                                      with SYEV3_FLAG_NEWTON */
-#define SYEV3_FLAG_REFINE_CONVERGE 16u /* FP32 storage: after the FP64 Newton
-                                     step, continue every root with FP64
-                                     Borges-Gragg steps (Sec. 1.4.1) until
-                                     their stop test, as is otherwise done
-                                     only when the Newton correction exceeds
-                                     2^-12 of the root.  Eigenvalues as
+#define SYEV3_FLAG_REFINE_CONVERGE 16u /* FP32 storage: after the first FP64
+                                     Newton step, continue every root with
+                                     FP64 Borges-Gragg steps (Sec. 1.4.1)
+                                     until their stop test, as is otherwise
+                                     done only when the Newton correction
+                                     exceeds 2^-14 of the root.  Eigenvalues as
                                      accurate as the FP64 zero finder makes
                                      them, for one or two more FP64
                                      evaluations per root; SYEV3_F32_REFINE
