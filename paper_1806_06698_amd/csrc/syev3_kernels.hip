@@ -29,6 +29,7 @@ namespace syev3 {
 // close to 256.  The pure streaming reference is fastest in launch order,
 // so it keeps it.
 constexpr uint32_t kXcds = 8;
+constexpr int kWave = 64;  // gfx950 runs wave64
 constexpr uint32_t kXcdChunk = 256;
 constexpr uint32_t kChunkFromBlocks = 1u << 17;  // 2^25 matrices
 
@@ -407,11 +408,16 @@ __global__ __launch_bounds__(kBlock) void k_syev3_segments(const TickTable* __re
   const int nseg = t->nseg;
   const int64_t total_tiles = t->total_tiles;
   for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-    // last segment whose tile_begin <= tile (uniform across the workgroup)
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (t->seg[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    // The last segment whose tile_begin <= tile (uniform across the
+    // workgroup).  The table is in ascending tile_begin order, so its index
+    // is the count of segments starting at or before the tile, minus one:
+    // each lane tests one segment and a ballot counts them, 64 per round,
+    // one load's latency rather than a chain of dependent ones.
+    int lo = -1;
+    for (int base = 0; base < nseg; base += kWave) {
+      const int j = base + (int)(threadIdx.x % kWave);
+      const bool le = j < nseg && t->seg[j].tile_begin <= tile;
+      lo += __popcll(__ballot(le));
     }
     const Segment s = t->seg[lo];
     const int64_t t0 = (tile - s.tile_begin) * kBlock;  // the tile's first matrix
