@@ -290,6 +290,41 @@ def test_one_segment_per_tick(source):
         assert st["inflight_ticks_peak"] == 1
 
 
+def test_a_tick_of_many_segments(source):
+    """A tick of far more than 64 requests: the kernel finds each tile's
+    request by counting, 64 table entries per round, the requests that start
+    at or before it.  The first request's ready event waits behind a short
+    spin on the GPU (one tick slot), so the next 200 requests queue up and
+    leave in one tick; every result equals a separate solve bitwise, and a
+    sample of each meets the oracle's bars."""
+    A64, A32 = source
+    rng = np.random.default_rng(11)
+    with serve.Server(hbm_budget_bytes=1 << 30, max_inflight_ticks=1,
+                      max_segments_per_tick=256) as srv:
+        first = srv.acquire(4096, s3.F64)
+        torch.cuda._sleep(100_000_000)  # about 50 ms at the GPU's clock
+        srv.submit(first, _fill(first, A64, 0))
+        reqs, off = [], 4096
+        for k in range(200):
+            n = int(rng.integers(1, 3000))
+            dt = s3.F64 if k % 2 == 0 else s3.F32_REFINE
+            r = srv.acquire(n, dt, vectors=k % 5 != 4)
+            srv.submit(r, _fill(r, A64 if dt == s3.F64 else A32, off))
+            off += n
+            reqs.append(r)
+        for r in [first] + reqs:
+            srv.wait(r, timeout_s=60.0)
+            _check_bitwise(r)
+        for r in reqs[::20]:
+            _check_oracle(r, sample=3000, label="many-segment tick")
+        for r in [first] + reqs:
+            srv.release(r)
+        st = srv.stats()
+        print(f"  ticks {st['ticks']}, segments per tick at peak "
+              f"{st['segments_per_tick_peak']}", flush=True)
+        assert st["segments_per_tick_peak"] > 128
+
+
 def test_caller_may_drop_its_ready_event_right_after_submit(source):
     """The server waits for the caller's event during submit and keeps a
     mark of its own, so a caller that destroys its event (or records it
