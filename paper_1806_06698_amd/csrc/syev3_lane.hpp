@@ -647,6 +647,22 @@ __device__ __forceinline__ Vec3 axpy(double s, const Vec3& a, const Vec3& b) {
               __builtin_fma(s, a.z, b.z)};
 }
 
+// max(|x|, |y|) and max(x, y) as one v_max_f64 each.  Written with
+// __builtin_fmax, each input loaded from memory first gets a canonicalising
+// v_max_f64 x, x of its own (fmax must quiet a signalling NaN), 11
+// instructions for the six-entry maximum instead of 5.  The maximum only
+// sets the scaling exponent; a NaN input is caught by the finiteness test.
+__device__ __forceinline__ double vmax_abs(double x, double y) {
+  double r;
+  asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(x), "v"(y));
+  return r;
+}
+__device__ __forceinline__ double vmax(double x, double y) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(x), "v"(y));
+  return r;
+}
+
 template <bool VECS, int FORM>
 __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
                                       double (&lam)[3], double (&V)[9], bool& bad) {
@@ -660,9 +676,7 @@ __device__ __forceinline__ int solve3(const double (&ain)[6], uint32_t flags,
   uint32_t badw = finite ? 0u : 1u;
   asm volatile("" : "+v"(badw));
   bad = badw != 0u;
-  const double m = __builtin_fmax(__builtin_fmax(__builtin_fmax(dabs(a11), dabs(a12)),
-                                                 __builtin_fmax(dabs(a13), dabs(a22))),
-                                  __builtin_fmax(dabs(a23), dabs(a33)));
+  const double m = vmax(vmax(vmax_abs(a11, a12), vmax_abs(a13, a22)), vmax_abs(a23, a33));
   // scale by 2^-e so that max |a_ij| is in [1/2, 1); m == 0 keeps e = 0
   // (kFlagNoScale, a uniform flag: e = 0, the unscaled matrix)
   // (The flags are the same for every lane: their alternatives are taken in
