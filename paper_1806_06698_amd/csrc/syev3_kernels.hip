@@ -358,9 +358,10 @@ hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout,
 // ---------------------------------------------------------------------------
 // Serving: one launch solves every request of a tick.  The grid is
 // persistent-style (sized to the device, not to the work): workgroups stride
-// over the tick's tiles; a tile is kBlock matrices of one segment, found by a
-// binary search of the (small) table, so each wavefront runs one dtype and
-// one code path.  Per-matrix arithmetic is exactly the batched kernels'.
+// over the tick's tiles; a tile is kBlock matrices of one segment, found in
+// the (small) table by one ballot per 64 entries, so each wavefront runs one
+// dtype and one code path.  Per-matrix arithmetic is exactly the batched
+// kernels' (eigenvalues do not depend on whether vectors are formed).
 // ---------------------------------------------------------------------------
 // One tile of segment s: matrices t0 .. t0 + kBlock - 1.  The tile's first
 // matrix is folded into the plane bases (uniform, in scalar registers), so

@@ -233,15 +233,15 @@ __device__ __forceinline__ double bg_start(const Arrow1& P, double rab) {
 }
 
 // FP32 versions (v_rcp_f32 and v_sqrt_f32 are accurate to about one ulp),
-// for the start of the FP64 iteration and of the FP32-storage form's Newton
-// step, and for the FP32 zero finder of the unrefined FP32 ablation.  The
-// FP64 iteration's start only has to be close: it converges from either
-// side (bg_step), and a start within about 1e-5 of the zero still needs a
-// single evaluation of f in FP64.  FP32 is cheaper than the FP64 sequences,
-// and the FP64 path is limited as much by the clock the chip sustains under
-// FP64 load as by HBM.
-// c0 = gb + b2^2/ab and rab = 1/ab, formed in FP64 and rounded, for the
-// FP32 zero finder of the unrefined form (unused by start_point).
+// for the start of the FP64 iteration, for the FP32 start and step that the
+// FP32-storage form's Newton step refines, and for the FP32 zero finder of
+// the unrefined FP32 ablation.  The FP64 iteration's start only has to be
+// close: it converges from either side (bg_step), and a start within about
+// 1e-5 of the zero still needs a single evaluation of f in FP64.  FP32 is
+// cheaper than the FP64 sequences, and the FP64 path is limited as much by
+// the clock the chip sustains under FP64 load as by HBM.
+// c0 = gb + b2^2/ab and rab = 1/ab, formed in FP64 and rounded, for the two
+// FP32-storage forms' chords and steps (unused by start_point).
 struct Arrow1f {
   float b1s, b2s, ab, gb;
   float c0 = 0.0f, rab = 0.0f;
