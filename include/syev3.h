@@ -141,6 +141,7 @@ extern "C" {
 #define SYEV3_E_STATE (-10)   /* server: bad handle or request state */
 #define SYEV3_E_TIMEOUT (-11) /* server: wait timed out */
 #define SYEV3_E_NOMEM (-12)   /* server: host memory could not be allocated */
+#define SYEV3_E_SEGMENTS (-13) /* more segments than the fixed table holds */
 
 /*
  * batched_syev3 -- eigenvalues (and eigenvectors if V != NULL) of n
@@ -379,6 +380,57 @@ int syev3_server_wait(syev3_server* s, int64_t request, double timeout_s,
 int syev3_server_release(syev3_server* s, int64_t request);
 
 int syev3_server_get_stats(syev3_server* s, syev3_server_stats* out);
+
+/* ------------------------------------------------------------------------
+ * A tick without the server, allocating nothing
+ * ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Solves
+ * nseg independent requests of different sizes and forms in one launch of
+ * the kernel that runs a server's ticks, on buffers the caller owns.  That
+ * kernel reads a table of the requests; a server allocates one per tick
+ * slot in syev3_server_create, this call uses a fixed array of the library
+ * in each GPU's memory instead (room for SYEV3_SEGMENTS_MAX segments, about
+ * 56 KiB, held until the process ends) and makes no hipMalloc, hipFree or
+ * other allocating call.  Results are bitwise those of the same requests
+ * served by a server or solved by batched_syev3_strided.
+ *
+ * segs[i]: n >= 0 matrices of dtype SYEV3_F64 or SYEV3_F32_REFINE; A holds
+ * 6 SoA planes at plane stride lda elements (0 means n, else >= n); lambda
+ * 3 planes and V 9 planes (NULL: eigenvalues only) at plane stride n; flags
+ * as for batched_syev3_ex.  All device memory of the stream's device.
+ * Segments with n == 0 are skipped.  The table is built from segs on the
+ * host and copied to the device from pageable host memory, which HIP does
+ * synchronously with respect to the host: segs may be reused as soon as
+ * the call returns.  The solve is enqueued on `stream`.
+ *
+ * Every call on one GPU uses that GPU's one table, which keeps the last
+ * call's contents (each call writes all of the table it reads).  Calls in
+ * one stream's order are safe; calls that overlap on one GPU (on streams
+ * not ordered with each other) race, and a kernel may then read a table
+ * that another call has overwritten.
+ *
+ * Returns SYEV3_OK (nothing is enqueued when every n is 0); SYEV3_E_SEGMENTS
+ * for nseg < 0 or nseg > SYEV3_SEGMENTS_MAX; SYEV3_E_NULL for segs == NULL
+ * with nseg > 0; per segment the errors of batched_syev3_strided, with
+ * SYEV3_F32 answered SYEV3_E_DTYPE; SYEV3_E_ALIAS also when an output of
+ * one segment overlaps an input or an output of another; SYEV3_E_HIP when
+ * the copy or the launch fails.  Nothing is enqueued on an argument error.
+ */
+#define SYEV3_SEGMENTS_MAX SYEV3_SERVER_MAX_SEGMENTS
+
+typedef struct {
+  int64_t n;
+  const void* A;   /* 6 planes, plane stride lda */
+  int64_t lda;
+  void* lambda;    /* 3 planes, plane stride n */
+  void* V;         /* 9 planes, plane stride n, or NULL */
+  int32_t dtype;
+  uint32_t flags;
+} syev3_segment;
+
+int syev3_solve_segments_noalloc(int32_t nseg, const syev3_segment* segs,
+                                 hipStream_t stream);
 
 /*
  * Load generator for a server (benchmark support).  Open loop (qps > 0):

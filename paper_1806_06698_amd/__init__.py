@@ -22,7 +22,7 @@ from ._lib import (AOS, AOS9, F32, F32_REFINE, F64, FLAG_NEWTON, FLAG_NO_H_GUARD
                    Syev3Error)
 
 __all__ = ["syev3", "syev3_inplace", "batched_syev3", "batched_syev3_ex", "batched_syev3_info",
-           "batched_syev3_strided",
+           "batched_syev3_strided", "syev3_solve_segments_noalloc",
            "F64", "F32_REFINE", "F32", "SOA", "AOS", "AOS9", "FLAG_SIMPLIFIED_DEFLATION",
            "FLAG_NO_H_GUARD", "FLAG_NEWTON", "FLAG_PAPER_BG", "FLAG_REFINE_CONVERGE", "FLAG_NO_SCALE",
            "Syev3Error",
@@ -66,6 +66,40 @@ def batched_syev3_strided(n, A_ptr, lda, lam_ptr, ldl, V_ptr, ldv, dtype, flags,
                           stream_handle) -> int:
     return _lib.lib().batched_syev3_strided(n, A_ptr, lda, lam_ptr, ldl, V_ptr, ldv, dtype,
                                             flags, stream_handle)
+
+
+def syev3_solve_segments_noalloc(segments, *, stream=None) -> None:
+    """Solve several independent requests in one launch, allocating nothing
+    (C ABI syev3_solve_segments_noalloc).  segments: (A, lam, V) or (A, lam,
+    V, flags) per request, all on one GPU: A (6, n) float64 (FP64) or float32
+    (FP32 storage + FP64 refinement) with unit column stride and row stride
+    >= n; lam (3, n) and V (9, n) or None, contiguous, of A's dtype; they are
+    written in place.  Asynchronous on the stream; calls on one GPU that are
+    not ordered on one stream race (they share the library's segment
+    table)."""
+    segs = (_lib.Segment * max(len(segments), 1))()
+    device = None
+    for i, item in enumerate(segments):
+        A, lam, V = item[:3]
+        flags = item[3] if len(item) > 3 else 0
+        if not A.is_cuda:
+            raise ValueError("segment inputs must be GPU tensors")
+        if device is None:
+            device = A.device
+        elif A.device != device:
+            raise ValueError("all segments must be on one device")
+        dt = _dtype_code(A)
+        n, ld = _soa_geometry(A)
+        for name, t, rows in (("lam", lam, 3), ("V", V, 9)):
+            if t is None and name == "V":
+                continue
+            _check_out(t, (rows, n), (n, 1), A, f"segment {i} {name}")
+        segs[i] = _lib.Segment(n, _ptr(A).value, ld, _ptr(lam).value, _ptr(V).value, dt, flags)
+    if device is None:
+        return
+    rc = _lib.lib().syev3_solve_segments_noalloc(len(segments), segs,
+                                                _stream_handle(stream, device))
+    _lib.check(rc, "syev3_solve_segments_noalloc")
 
 
 def _dtype_code(t: torch.Tensor, refine: bool = True) -> int:

@@ -27,8 +27,9 @@ FLAG_NO_SCALE = 32
 E = {
     0: "OK", -1: "E_N", -2: "E_NULL", -3: "E_DTYPE", -4: "E_LAYOUT",
     -5: "E_ALIAS", -6: "E_HIP", -7: "E_FLAGS", -8: "E_BUDGET", -9: "E_AGAIN",
-    -10: "E_STATE", -11: "E_TIMEOUT", -12: "E_NOMEM",
+    -10: "E_STATE", -11: "E_TIMEOUT", -12: "E_NOMEM", -13: "E_SEGMENTS",
 }
+SEGMENTS_MAX = 1024
 E_AGAIN = -9
 
 
@@ -55,6 +56,13 @@ class RequestBuffers(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("lam", ctypes.c_void_p),
                 ("V", ctypes.c_void_p), ("n", ctypes.c_int64),
                 ("dtype", ctypes.c_int32)]
+
+
+class Segment(ctypes.Structure):
+    """syev3_segment: one request of syev3_solve_segments_noalloc."""
+    _fields_ = [("n", ctypes.c_int64), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("lam", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("dtype", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -96,6 +104,8 @@ def lib() -> ctypes.CDLL:
     L.syev3_stream_reference.restype = i32
     L.syev3_stream_probe.argtypes = [i64, vp, vp, vp, i32, u32, vp]
     L.syev3_stream_probe.restype = i32
+    L.syev3_solve_segments_noalloc.argtypes = [i32, ctypes.POINTER(Segment), vp]
+    L.syev3_solve_segments_noalloc.restype = i32
     L.syev3_strerror.argtypes = [i32]
     L.syev3_strerror.restype = ctypes.c_char_p
     L.syev3_version.argtypes = []

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsyev3.so")
 
-SOURCES = ["syev3_kernels.hip", "syev3_api.cpp", "syev3_server.cpp"]
+SOURCES = ["syev3_kernels.hip", "syev3_noalloc.hip", "syev3_api.cpp", "syev3_server.cpp"]
 
 ARCH = os.environ.get("SYEV3_OFFLOAD_ARCH", "gfx950")
 

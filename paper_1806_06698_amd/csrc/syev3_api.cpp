@@ -4,6 +4,9 @@
 
 #include <stdint.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "syev3_internal.hpp"
 
 namespace {
@@ -91,9 +94,75 @@ int solve(int64_t n, const void* A, syev3::Strides ld, int layout, void* lambda,
   return e == hipSuccess ? SYEV3_OK : SYEV3_E_HIP;
 }
 
+// Host image of the no-allocation entry point's segment table and the
+// output ranges its alias check sorts: static, so that the call allocates
+// nothing; one call at a time fills them (the table copy completes before
+// the call returns).
+std::mutex g_seg_mu;
+syev3::TickTable g_seg_table;
+Range g_seg_out[2 * SYEV3_SEGMENTS_MAX];
+
+int solve_segments(int32_t nseg, const syev3_segment* segs, hipStream_t stream) {
+  if (nseg < 0 || nseg > SYEV3_SEGMENTS_MAX) return SYEV3_E_SEGMENTS;
+  if (nseg > 0 && !segs) return SYEV3_E_NULL;
+  std::lock_guard<std::mutex> lock(g_seg_mu);
+  syev3::TickTable& t = g_seg_table;
+  int k = 0, nout = 0;
+  int64_t tiles = 0;
+  for (int i = 0; i < nseg; ++i) {
+    const syev3_segment& q = segs[i];
+    // the segment kernel holds the FP64 and the refined FP32 form
+    if (q.dtype != SYEV3_F64 && q.dtype != SYEV3_F32_REFINE) return SYEV3_E_DTYPE;
+    syev3::Strides ld{q.lda, 0, 0};
+    const int rc = check_args(q.n, q.A, ld, SYEV3_SOA, q.lambda, q.V, q.dtype, q.flags);
+    if (rc != SYEV3_OK) return rc;
+    if (q.n == 0) continue;
+    const size_t es = q.dtype == SYEV3_F64 ? sizeof(double) : sizeof(float);
+    g_seg_out[nout++] = span(q.lambda, q.n, q.n, SYEV3_SOA, 3, es);
+    if (q.V) g_seg_out[nout++] = span(q.V, q.n, q.n, SYEV3_SOA, 9, es);
+    syev3::Segment& g = t.seg[k++];
+    g.A = q.A;
+    g.lambda = q.lambda;
+    g.V = q.V;
+    g.n = q.n;
+    g.lda = ld.a;
+    g.tile_begin = tiles;
+    g.dtype = q.dtype;
+    g.flags = q.flags;
+    tiles += (q.n + syev3::kBlock - 1) / syev3::kBlock;
+  }
+  // Across segments: the outputs pairwise disjoint (sorted by start, each
+  // ends before the next begins), and no input overlapping an output (the
+  // last output starting below the input's end is the only candidate).
+  // Inputs may share memory: they are only read.
+  std::sort(g_seg_out, g_seg_out + nout,
+            [](const Range& x, const Range& y) { return x.lo < y.lo; });
+  for (int i = 1; i < nout; ++i)
+    if (overlap(g_seg_out[i - 1], g_seg_out[i])) return SYEV3_E_ALIAS;
+  for (int i = 0; i < k; ++i) {
+    const syev3::Segment& g = t.seg[i];
+    const size_t es = g.dtype == SYEV3_F64 ? sizeof(double) : sizeof(float);
+    const Range ra = span(g.A, g.n, g.lda, SYEV3_SOA, 6, es);
+    const Range* o = std::upper_bound(g_seg_out, g_seg_out + nout, ra.hi,
+                                      [](uintptr_t v, const Range& x) { return v <= x.lo; });
+    if (o != g_seg_out && overlap(o[-1], ra)) return SYEV3_E_ALIAS;
+  }
+  t.nseg = k;
+  t.reserved = 0;
+  t.total_tiles = tiles;
+  if (tiles == 0) return SYEV3_OK;
+  (void)hipGetLastError();  // a stale error is not this call's
+  return syev3::launch_segments_noalloc(&t, stream) == hipSuccess ? SYEV3_OK : SYEV3_E_HIP;
+}
+
 }  // namespace
 
 extern "C" {
+
+int syev3_solve_segments_noalloc(int32_t nseg, const syev3_segment* segs,
+                                 hipStream_t stream) {
+  return solve_segments(nseg, segs, stream);
+}
 
 int batched_syev3_info(int64_t n, const void* A, int64_t ld, int layout,
                        void* lambda, void* V, int dtype, uint32_t flags,
@@ -162,6 +231,7 @@ const char* syev3_strerror(int code) {
     case SYEV3_E_STATE: return "invalid server handle or request state";
     case SYEV3_E_TIMEOUT: return "timed out waiting for the request";
     case SYEV3_E_NOMEM: return "server: out of host memory";
+    case SYEV3_E_SEGMENTS: return "segment count outside 0 .. SYEV3_SEGMENTS_MAX";
     default: return "unknown error code";
   }
 }

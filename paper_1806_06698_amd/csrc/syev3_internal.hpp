@@ -61,6 +61,12 @@ inline size_t tick_table_bytes(int max_segments) {
 hipError_t launch_segments(const TickTable* table, int32_t grid_blocks,
                            hipStream_t stream);
 
+// The same on the library's fixed per-device table (no allocation): copies
+// host_table (nseg segments, total_tiles > 0) into the table of the stream's
+// device, then launches on it.  The copy is from pageable host memory, which
+// HIP completes before returning.
+hipError_t launch_segments_noalloc(const TickTable* host_table, hipStream_t stream);
+
 // Device properties used for grid sizing.
 int device_cu_count();
 

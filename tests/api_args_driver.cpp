@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <random>
+#include <vector>
 
 namespace {
 struct Launch {
@@ -40,6 +41,16 @@ hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout, void
 hipError_t launch_stream_probe(int64_t n, const void* A, void* lambda, void* V, int dtype,
                                uint32_t, hipStream_t) {
   g_launch = Launch{g_launch.count + 1, n, n, n, n, 0, dtype, A, lambda, V, 0u, nullptr};
+  return hipSuccess;
+}
+// the no-allocation segment call: a copy of the table it would upload
+int g_seg_launches = 0;
+TickTable g_seg_seen;
+hipError_t launch_segments_noalloc(const TickTable* t, hipStream_t) {
+  ++g_seg_launches;
+  g_seg_seen.nseg = t->nseg;
+  g_seg_seen.total_tiles = t->total_tiles;
+  for (int i = 0; i < t->nseg && i < kMaxSegmentsPerTick; ++i) g_seg_seen.seg[i] = t->seg[i];
   return hipSuccess;
 }
 }  // namespace syev3
@@ -101,6 +112,104 @@ int failures = 0;
 long long n_launched = 0, n_rejected = 0, n_noop = 0, n_modelled = 0;
 void fail(const char* what, long long i) {
   if (failures++ < 20) std::fprintf(stderr, "case %lld: %s\n", i, what);
+}
+
+// syev3_solve_segments_noalloc: random lists of segments (mostly short, so
+// the model's all-pairs alias test stays cheap; now and then the longest
+// accepted and one more).  Accepted exactly when every segment passes the
+// batched rules (SoA, outputs at stride n, FP64 or FP32-refined only) and
+// no output of any segment overlaps an input or output of another; then the
+// launcher gets the non-empty segments in order with their tile ranges.
+long long n_seg_launched = 0, n_seg_rejected = 0;
+long long segment_cases(std::mt19937_64& rng, long long cases) {
+  auto pick = [&](std::initializer_list<int64_t> v) { return *(v.begin() + rng() % v.size()); };
+  const uint64_t base = (uint64_t)1 << 44;
+  static syev3_segment segs[SYEV3_SEGMENTS_MAX + 1];
+  for (long long i = 0; i < cases; ++i) {
+    const int roll = (int)(rng() % 100);
+    const int nseg = roll == 0 ? SYEV3_SEGMENTS_MAX : roll == 1 ? SYEV3_SEGMENTS_MAX + 1
+                   : roll == 2 ? -1 : (int)(rng() % 9);
+    const int made = nseg < 0 ? 0 : nseg;
+    // the long lists, and half of the short ones: valid segments in separate
+    // regions (accepted: their tables are checked)
+    const bool big = nseg > 16 || rng() % 2 == 0;
+    for (int k = 0; k < made; ++k) {
+      syev3_segment& q = segs[k];
+      q.n = nseg > 16 ? pick({0, 1, 300}) : big ? pick({0, 1, 255, 256, 257, 1000})
+                                           : pick({-2, 0, 1, 255, 256, 257, 1000});
+      q.lda = big ? 0 : pick({0, 0, q.n, q.n + 3, q.n - 1});
+      q.dtype = big ? (int32_t)(rng() % 2) : (int32_t)pick({0, 0, 1, 1, 2, -1});
+      q.flags = big ? 0u : (uint32_t)pick({0, 0, 0, 1, 4, 16, 32, 64});
+      // each segment in its own region, or (short lists) near or inside
+      // another segment's arrays; 0 for NULL now and then
+      auto addr = [&](int slot) -> uint64_t {
+        const uint64_t own = base + ((uint64_t)(4 * k + slot) << 32);
+        if (big) return own;
+        switch (rng() % 8) {
+          case 0: return 0;
+          case 1: return base + ((uint64_t)(rng() % 32) << 32) + (uint64_t)(rng() % 2048) * 8;
+          case 2:
+          case 3: {
+            // into an array of an earlier segment
+            if (k == 0) return own;
+            const syev3_segment& e = segs[rng() % k];
+            const uint64_t p = (uint64_t)(rng() % 3 == 0 ? e.A : rng() % 2 ? (const void*)e.lambda
+                                                                            : (const void*)e.V);
+            return p ? p + (uint64_t)(rng() % 64) * 8 : own;
+          }
+          default: return own + (uint64_t)(rng() % 16) * 8;
+        }
+      };
+      q.A = (const void*)addr(0);
+      q.lambda = (void*)addr(1);
+      q.V = rng() % 5 == 0 ? nullptr : (void*)addr(2);
+    }
+    syev3::g_seg_launches = 0;
+    const int rc = syev3_solve_segments_noalloc(nseg, nseg >= 0 ? segs : nullptr, nullptr);
+    // the model
+    bool ok = nseg >= 0 && nseg <= SYEV3_SEGMENTS_MAX;
+    std::vector<Span> outs, ins;
+    for (int k = 0; ok && k < nseg; ++k) {
+      const syev3_segment& q = segs[k];
+      if (q.dtype != 0 && q.dtype != 1) ok = false;
+      else if (!model_valid(q.n, (uint64_t)q.A, q.lda, 0, 0, 0, (uint64_t)q.lambda,
+                            (uint64_t)q.V, q.dtype, q.flags, 0, false)) ok = false;
+      if (!ok || q.n <= 0) continue;
+      const int es = q.dtype == 0 ? 8 : 4;
+      ins.push_back(span_of((uint64_t)q.A, q.n, q.lda ? q.lda : q.n, 0, 6, es));
+      outs.push_back(span_of((uint64_t)q.lambda, q.n, q.n, 0, 3, es));
+      if (q.V) outs.push_back(span_of((uint64_t)q.V, q.n, q.n, 0, 9, es));
+    }
+    for (size_t a = 0; ok && a < outs.size(); ++a) {
+      for (size_t b = a + 1; ok && b < outs.size(); ++b) ok = !hits(outs[a], outs[b]);
+      for (size_t b = 0; ok && b < ins.size(); ++b) ok = !hits(outs[a], ins[b]);
+    }
+    n_seg_rejected += rc != SYEV3_OK;
+    n_seg_launched += syev3::g_seg_launches;
+    if (ok != (rc == SYEV3_OK)) fail(ok ? "valid segment call rejected" : "invalid segment call accepted", i);
+    if (rc != SYEV3_OK && syev3::g_seg_launches) fail("segment call rejected but launched", i);
+    if (rc != SYEV3_OK && (rc > -1 || rc < -13 || rc == SYEV3_E_HIP))
+      fail("undocumented code from the segment call", i);
+    if (rc == SYEV3_OK) {
+      int want = 0;
+      int64_t tiles = 0;
+      bool same = true;
+      for (int k = 0; k < nseg; ++k) {
+        const syev3_segment& q = segs[k];
+        if (q.n == 0) continue;
+        const syev3::Segment& g = syev3::g_seg_seen.seg[want++];
+        same = same && g.A == q.A && g.lambda == q.lambda && g.V == q.V && g.n == q.n &&
+               g.lda == (q.lda ? q.lda : q.n) && g.tile_begin == tiles && g.dtype == q.dtype &&
+               g.flags == q.flags;
+        tiles += (q.n + 255) / 256;
+      }
+      if (syev3::g_seg_launches != (tiles > 0 ? 1 : 0)) fail("segment launch count", i);
+      if (tiles > 0 && (!same || syev3::g_seg_seen.nseg != want ||
+                        syev3::g_seg_seen.total_tiles != tiles))
+        fail("segment table differs from the call", i);
+    }
+  }
+  return cases;
 }
 
 }  // namespace
@@ -217,7 +326,11 @@ int main(int argc, char** argv) {
       if (ok != (rc == SYEV3_OK)) fail(ok ? "valid call rejected" : "invalid call accepted", i);
     }
   }
+  const int case_failures = failures;
+  const long long seg_cases = segment_cases(rng, cases / 10);
   std::printf("%lld cases (%lld launched, %lld rejected, %lld no-op; %lld against the model), "
-              "%d failures\n", cases, n_launched, n_rejected, n_noop, n_modelled, failures);
+              "%d failures; %lld segment calls (%lld launched, %lld rejected), %d failures\n",
+              cases, n_launched, n_rejected, n_noop, n_modelled, case_failures, seg_cases,
+              n_seg_launched, n_seg_rejected, failures - case_failures);
   return failures ? 1 : 0;
 }

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_function(L):
 
 
 def test_strerror_and_version(L):
-    for code in range(0, -13, -1):
+    for code in range(0, -14, -1):
         s = L.syev3_strerror(code).decode()
         assert s and s != "unknown error code"
     assert L.syev3_version() >= 10000
@@ -111,6 +111,51 @@ def test_bad_arguments_are_rejected(L, no_device):
     assert inplace(10, A, ctypes.c_void_p(0x100000 + 8 * 10), 0, S) == -5
     # huge n for the grid
     assert ex(1 << 62, A, 0, 0, LAM, VV, 0, 0, S) in (-1, -4)
+
+
+def test_segment_call_rejects_bad_arguments(L, no_device):
+    """syev3_solve_segments_noalloc: the segment count against the fixed
+    table, the per-segment rules of the batched calls (SYEV3_F32, which the
+    segment kernel lacks, included) and aliasing across segments, all
+    answered before any HIP call."""
+    from paper_1806_06698_amd._lib import Segment, SEGMENTS_MAX
+    call = L.syev3_solve_segments_noalloc
+
+    def seg(n=10, a=0x100000, lda=0, lam=0x200000, v=0x300000, dtype=0, flags=0):
+        return Segment(n, a, lda, lam, v, dtype, flags)
+
+    def run(*segs, nseg=None):
+        arr = (Segment * max(len(segs), 1))(*segs)
+        rc = call(len(segs) if nseg is None else nseg, arr, S)
+        assert rc in ARG_ERRORS | {-13}, f"rc={rc}: the call got past argument checking"
+        return rc
+
+    assert run(seg(), nseg=-1) == -13
+    assert run(seg(), nseg=SEGMENTS_MAX + 1) == -13
+    assert call(1, None, S) == -2
+    assert run(seg(dtype=2)) == -3                    # the unrefined ablation
+    assert run(seg(dtype=7)) == -3
+    assert run(seg(flags=128)) == -7
+    assert run(seg(lda=5)) == -4
+    assert run(seg(n=-1)) == -1
+    assert run(seg(a=0)) == -2
+    assert run(seg(lam=0x100000 + 8 * 30)) == -5      # inside its own input
+    # across segments: an output inside another segment's input, outputs
+    # overlapping each other
+    assert run(seg(), seg(a=0x400000, lam=0x100000 + 8, v=0)) == -5
+    assert run(seg(), seg(a=0x400000, lam=0x500000, v=0x300000 + 8 * 80)) == -5
+    assert run(seg(), seg(a=0x400000, lam=0x200000, v=0)) == -5
+    # a bad segment after valid ones rejects the whole call
+    assert run(seg(), seg(a=0x400000, lam=0x500000, v=0x600000, dtype=3)) == -3
+
+
+def test_segment_call_with_nothing_to_solve_is_a_noop(L):
+    """No segments, or only empty ones: accepted, nothing enqueued (no HIP
+    call is made, so this holds without a GPU too)."""
+    from paper_1806_06698_amd._lib import Segment
+    empty = (Segment * 2)(Segment(0, 0, 0, 0, 0, 0, 0), Segment(0, 0, 0, 0, 0, 1, 0))
+    assert L.syev3_solve_segments_noalloc(0, None, S) == 0
+    assert L.syev3_solve_segments_noalloc(2, empty, S) == 0
 
 
 def test_n_zero_is_a_noop(L):

@@ -59,3 +59,19 @@ def test_the_driver_catches_a_missing_alias_check(tmp_path):
     exe = _build(tmp_path, str(mut), "api_args_mutant")
     p = _run(exe, 50_000)
     assert p.returncode != 0 and "invalid call accepted" in p.stderr
+
+
+def test_the_driver_catches_a_missing_cross_segment_alias_check(tmp_path):
+    """The same for the segment call: with its check of inputs against other
+    segments' outputs removed, the driver must report an accepted call that
+    the documented rules forbid."""
+    _need_toolchain()
+    src = open(os.path.join(ROOT, "paper_1806_06698_amd", "csrc", "syev3_api.cpp")).read()
+    old = "    if (o != g_seg_out && overlap(o[-1], ra)) return SYEV3_E_ALIAS;"
+    assert src.count(old) == 1
+    mut = tmp_path / "mutant"
+    mut.mkdir()
+    (mut / "syev3_api.cpp").write_text(src.replace(old, "    (void)o;"))
+    exe = _build(tmp_path, str(mut), "api_segments_mutant")
+    p = _run(exe, 100_000)
+    assert p.returncode != 0 and "invalid segment call accepted" in p.stderr
