@@ -67,7 +67,4 @@ hipError_t launch_segments(const TickTable* table, int32_t grid_blocks,
 // HIP completes before returning.
 hipError_t launch_segments_noalloc(const TickTable* host_table, hipStream_t stream);
 
-// Device properties used for grid sizing.
-int device_cu_count();
-
 }  // namespace syev3

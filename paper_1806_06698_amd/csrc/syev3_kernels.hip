@@ -356,12 +356,12 @@ hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout,
 }
 
 // ---------------------------------------------------------------------------
-// Serving: one launch solves every request of a tick.  The grid is
-// persistent-style (sized to the device, not to the work): workgroups stride
-// over the tick's tiles; a tile is kBlock matrices of one segment, found in
-// the (small) table by one ballot per 64 entries, so each wavefront runs one
-// dtype and one code path.  Per-matrix arithmetic is exactly the batched
-// kernels' (eigenvalues do not depend on whether vectors are formed).
+// Serving: one launch solves every request of a tick.  A tile is kBlock
+// matrices of one segment, so each wavefront runs one dtype and one code
+// path; the launch has one workgroup per tile unless its grid is capped, in
+// which case workgroups stride over the tiles.  Per-matrix arithmetic is
+// exactly the batched kernels' (eigenvalues do not depend on whether
+// vectors are formed).
 // ---------------------------------------------------------------------------
 // One tile of segment s: matrices t0 .. t0 + kBlock - 1.  The tile's first
 // matrix is folded into the plane bases (uniform, in scalar registers), so
@@ -408,18 +408,32 @@ __device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t t0)
 __global__ __launch_bounds__(kBlock) void k_syev3_segments(const TickTable* __restrict__ t) {
   const int nseg = t->nseg;
   const int64_t total_tiles = t->total_tiles;
+  // A tile's segment is the last whose tile_begin <= tile (uniform across
+  // the workgroup).  The table is in ascending tile_begin order, so its index
+  // is the count of segments starting at or before the tile, minus one: each
+  // lane tests four segments and ballots count them, kRound per round, with
+  // the four loads in flight together.  A round not all of whose segments
+  // start at or before the tile is the last.  A workgroup's tiles ascend, so
+  // its next search starts at the round that held this tile's segment.
+  constexpr int kRound = 4 * kWave;
+  int from = 0;  // a multiple of kRound; every segment before it qualifies
   for (int64_t tile = blockIdx.x; tile < total_tiles; tile += gridDim.x) {
-    // The last segment whose tile_begin <= tile (uniform across the
-    // workgroup).  The table is in ascending tile_begin order, so its index
-    // is the count of segments starting at or before the tile, minus one:
-    // each lane tests one segment and a ballot counts them, 64 per round,
-    // one load's latency rather than a chain of dependent ones.
-    int lo = -1;
-    for (int base = 0; base < nseg; base += kWave) {
-      const int j = base + (int)(threadIdx.x % kWave);
-      const bool le = j < nseg && t->seg[j].tile_begin <= tile;
-      lo += __popcll(__ballot(le));
+    int cnt = from;
+    for (int base = from; base < nseg; base += kRound) {
+      int64_t tb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = base + u * kWave + (int)(threadIdx.x % kWave);
+        tb[u] = j < nseg ? t->seg[j].tile_begin : INT64_MAX;
+      }
+      int c = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c += __popcll(__ballot(tb[u] <= tile));
+      cnt += c;
+      if (c < kRound) break;
     }
+    const int lo = cnt - 1;
+    from = lo / kRound * kRound;
     const Segment s = t->seg[lo];
     const int64_t t0 = (tile - s.tile_begin) * kBlock;  // the tile's first matrix
     if (t0 + threadIdx.x < s.n) {
@@ -504,14 +518,6 @@ hipError_t launch_stream_probe(int64_t n, const void* A, void* lambda, void* V, 
                                          stream)
            : launch_probe_t<float, false>(n, (const float*)A, (float*)lambda, nullptr, mode,
                                           stream);
-}
-
-int device_cu_count() {
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 256;
-  return cus > 0 ? cus : 256;
 }
 
 }  // namespace syev3

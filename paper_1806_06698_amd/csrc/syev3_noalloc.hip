@@ -58,12 +58,8 @@ hipError_t launch_segments_noalloc(const TickTable* host_table, hipStream_t stre
   e = hipMemcpyAsync(table, host_table, tick_table_bytes(host_table->nseg),
                      hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return e;
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      cus <= 0)
-    cus = 256;
-  // the server's grid (32 workgroups per compute unit), or one per tile
-  const int64_t grid = std::min<int64_t>(host_table->total_tiles, (int64_t)cus * 32);
+  // one workgroup per tile (as a server's ticks), up to 2^24
+  const int64_t grid = std::min<int64_t>(host_table->total_tiles, (int64_t)1 << 24);
   (void)hipGetLastError();  // launch_segments reads it: drop any stale error
   return launch_segments(table, (int32_t)grid, stream);
 }

@@ -91,6 +91,10 @@ struct TickSlot {
   syev3::TickTable* d_table = nullptr;  // device
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the captured kernel node and its parameters: the grid is set per tick
+  hipGraphNode_t knode = nullptr;
+  hipKernelNodeParams kparams{};
+  int32_t grid_set = 0;  // the grid the instantiated graph launches now
   std::vector<int> reqs;
   bool busy = false;
   // a profiler range from launch to observed completion
@@ -114,7 +118,13 @@ struct syev3_server {
   std::deque<int> queue;
   std::vector<TickSlot> ticks;
   size_t table_bytes = 0;
-  int grid_blocks = 0;
+  int64_t grid_cap = 0;  // most workgroups of one tick's launch
+
+  // Workgroups for a tick of `tiles` tiles: one per tile up to grid_cap
+  // (beyond it they stride over the tiles); at least one.
+  int32_t tick_grid(int64_t tiles) const {
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(tiles, grid_cap));
+  }
 
   std::mutex mu;
   std::condition_variable cv_sched, cv_done;
@@ -203,13 +213,20 @@ int syev3_server::launch_tick(int slot) {
   t->nseg = nseg;
   t->total_tiles = tiles;
   if (e == hipSuccess) {
+    const int32_t grid = tick_grid(tiles);
     if (tk.exec) {
-      e = hipGraphLaunch(tk.exec, tk.stream);
+      // the slot's previous tick has completed, so its graph may be changed
+      if (grid != tk.grid_set) {
+        tk.kparams.gridDim = dim3((unsigned)grid);
+        e = hipGraphExecKernelNodeSetParams(tk.exec, tk.knode, &tk.kparams);
+        if (e == hipSuccess) tk.grid_set = grid;
+      }
+      if (e == hipSuccess) e = hipGraphLaunch(tk.exec, tk.stream);
     } else {
       e = hipMemcpyAsync(tk.d_table, tk.h_table, table_bytes, hipMemcpyHostToDevice, tk.stream);
       // launch_segments reads hipGetLastError: clear any stale error first
       if (e == hipSuccess) (void)hipGetLastError();
-      if (e == hipSuccess) e = syev3::launch_segments(tk.d_table, grid_blocks, tk.stream);
+      if (e == hipSuccess) e = syev3::launch_segments(tk.d_table, grid, tk.stream);
     }
   }
   if (staged_out && e == hipSuccess) {
@@ -309,6 +326,9 @@ int syev3_server::init(const syev3_server_opts& opts) {
   if (hipGetDevice(&device) != hipSuccess) return SYEV3_E_HIP;
   if (hipMalloc((void**)&pool, o.hbm_budget_bytes) != hipSuccess) {
     pool = nullptr;
+    // reported as SYEV3_E_BUDGET: take the error off the thread's last-error
+    // state, where the caller's next launch check would find it as its own
+    (void)hipGetLastError();
     return SYEV3_E_BUDGET;
   }
   alloc = new syev3::PoolAllocator(o.hbm_budget_bytes);
@@ -321,11 +341,18 @@ int syev3_server::init(const syev3_server_opts& opts) {
   for (int k = o.max_requests - 1; k >= 0; --k) free_slots.push_back(k);
   done_ids.reserve(o.max_requests);
   table_bytes = syev3::tick_table_bytes(o.max_segments_per_tick);
-  // 32 workgroups per compute unit by default: on the stress-mix serving
-  // load (input views, 256 requests in flight) this served 3-10% more
-  // matrices per second than 8 per unit, with lower latency at 80% of
-  // saturation and the same at 2000 requests/s.
-  grid_blocks = o.grid_blocks > 0 ? o.grid_blocks : syev3::device_cu_count() * 32;
+  // By default one workgroup per tile of each tick.  A workgroup that goes
+  // on to a second tile waits, before that tile's loads complete, for the
+  // first tile's stores as well (one counter tracks both), which one that
+  // ends after its stores never does: on a tick of 202 stress-mix requests
+  // (16.8 M matrices) the kernel took 0.49 ms with one workgroup per tile
+  // against 0.59 ms with 32 per compute unit striding over the tiles, and
+  // the serving load (input views, 256 requests in flight) served 35.9
+  // against 33.0 G matrices/s with a fixed 32768 workgroups.  A fixed grid
+  // far above the tiles costs latency instead (workgroups with no tile:
+  // p50 at 2000 requests/s 0.07 ms with 131072, 0.15 ms with 524288), so
+  // the grid is sized per tick.
+  grid_cap = o.grid_blocks > 0 ? o.grid_blocks : (int64_t)1 << 24;
   ticks.resize(o.max_inflight_ticks);
   for (auto& tk : ticks) {
     tk.reqs.reserve(o.max_segments_per_tick);
@@ -342,10 +369,22 @@ int syev3_server::init(const syev3_server_opts& opts) {
         ok = hipMemcpyAsync(tk.d_table, tk.h_table, table_bytes, hipMemcpyHostToDevice,
                             tk.stream) == hipSuccess;
         (void)hipGetLastError();  // launch_segments reads it: drop any stale error
-        ok = ok && syev3::launch_segments(tk.d_table, grid_blocks, tk.stream) == hipSuccess;
+        ok = ok && syev3::launch_segments(tk.d_table, 1, tk.stream) == hipSuccess;
         const bool ended = hipStreamEndCapture(tk.stream, &tk.graph) == hipSuccess;
         ok = ok && ended;
       }
+      // the kernel node, whose grid each tick sets
+      size_t nn = 0;
+      ok = ok && hipGraphGetNodes(tk.graph, nullptr, &nn) == hipSuccess && nn <= 8;
+      hipGraphNode_t nodes[8];
+      ok = ok && hipGraphGetNodes(tk.graph, nodes, &nn) == hipSuccess;
+      for (size_t i = 0; ok && i < nn; ++i) {
+        hipGraphNodeType ty;
+        if (hipGraphNodeGetType(nodes[i], &ty) == hipSuccess && ty == hipGraphNodeTypeKernel)
+          tk.knode = nodes[i];
+      }
+      ok = ok && tk.knode && hipGraphKernelNodeGetParams(tk.knode, &tk.kparams) == hipSuccess;
+      tk.grid_set = 1;
       ok = ok && hipGraphInstantiate(&tk.exec, tk.graph, nullptr, nullptr, 0) == hipSuccess;
       if (!ok) return SYEV3_E_HIP;
     }
@@ -426,7 +465,7 @@ void syev3_server_default_opts(syev3_server_opts* o) {
   o->max_inflight_ticks = 4;
   o->max_segments_per_tick = 256;
   o->grid_blocks = 0;
-  o->use_graphs = 1;
+  o->use_graphs = 0;
 }
 
 int syev3_server_create(const syev3_server_opts* opts, syev3_server** out) {

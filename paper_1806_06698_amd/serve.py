@@ -127,7 +127,7 @@ def _tensor_at(ptr, shape, dtype, esize, dev):
 class Server:
     def __init__(self, hbm_budget_bytes=64 << 30, max_requests=4096,
                  max_inflight_ticks=4, max_segments_per_tick=256, grid_blocks=0,
-                 use_graphs=True):
+                 use_graphs=False):
         self.L = _bind(_lib.lib())
         o = ServerOpts()
         self.L.syev3_server_default_opts(ctypes.byref(o))

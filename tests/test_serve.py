@@ -86,11 +86,16 @@ def test_each_result_same_alone_and_in_the_mix(source, use_graphs):
         assert st["queue_depth"] == 0 and 1 <= st["queue_depth_peak"] <= len(sizes)
 
 
-def test_many_ticks_with_eager_work_between_replays(source):
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_many_ticks_with_eager_work_between_replays(source, use_graphs):
+    """Forty ticks of varying grids (one workgroup per tile: with graphs,
+    each replay first sets the captured kernel node's grid), with the
+    program's own eager work and a synchronisation between them."""
     A64, A32 = source
     rng = np.random.default_rng(2)
     scratch = torch.zeros(1 << 20, device="cuda")
-    with serve.Server(hbm_budget_bytes=1 << 30, max_inflight_ticks=2) as srv:
+    with serve.Server(hbm_budget_bytes=1 << 30, max_inflight_ticks=2,
+                      use_graphs=use_graphs) as srv:
         for it in range(40):
             reqs = []
             for _ in range(int(rng.integers(1, 5))):
@@ -251,7 +256,9 @@ def test_concurrent_clients(source):
 
 def test_create_failures_and_limits():
     """A pool larger than the device fails with SYEV3_E_BUDGET after freeing
-    what creation had made; the largest allowed max_requests works."""
+    what creation had made, and leaves no HIP error behind for the caller's
+    next launch (torch checks the last error after each); the largest
+    allowed max_requests works."""
     total = torch.cuda.get_device_properties(0).total_memory
     with pytest.raises(s3.Syev3Error) as exc:
         serve.Server(hbm_budget_bytes=total + (64 << 30))
@@ -290,22 +297,28 @@ def test_one_segment_per_tick(source):
         assert st["inflight_ticks_peak"] == 1
 
 
-def test_a_tick_of_many_segments(source):
-    """A tick of far more than 64 requests: the kernel finds each tile's
-    request by counting, 64 table entries per round, the requests that start
-    at or before it.  The first request's ready event waits behind a short
-    spin on the GPU (one tick slot), so the next 200 requests queue up and
-    leave in one tick; every result equals a separate solve bitwise, and a
-    sample of each meets the oracle's bars."""
+@pytest.mark.parametrize("nreq,grid_blocks,use_graphs", [(200, 0, False), (600, 7, True),
+                                                         (600, 0, False)])
+def test_a_tick_of_many_segments(source, nreq, grid_blocks, use_graphs):
+    """A tick of many requests: the kernel finds each tile's request by
+    counting, 256 table entries per round, the requests that start at or
+    before it.  The first request's ready event waits behind a short spin on
+    the GPU (one tick slot), so the next nreq requests queue up and leave in
+    one tick (600: three rounds of the count).  With the grid capped at 7
+    workgroups each strides over hundreds of tiles, its search resuming at
+    the round of its last tile.  Every result equals a separate solve
+    bitwise, and a sample meets the oracle's bars."""
     A64, A32 = source
     rng = np.random.default_rng(11)
     with serve.Server(hbm_budget_bytes=1 << 30, max_inflight_ticks=1,
-                      max_segments_per_tick=256) as srv:
+                      max_segments_per_tick=1024, grid_blocks=grid_blocks,
+                      use_graphs=use_graphs) as srv:
         first = srv.acquire(4096, s3.F64)
-        torch.cuda._sleep(100_000_000)  # about 50 ms at the GPU's clock
+        # about 50 ms per 200 requests at the GPU's clock, the time to queue them
+        torch.cuda._sleep(100_000_000 * (nreq // 200 + 1))
         srv.submit(first, _fill(first, A64, 0))
         reqs, off = [], 4096
-        for k in range(200):
+        for k in range(nreq):
             n = int(rng.integers(1, 3000))
             dt = s3.F64 if k % 2 == 0 else s3.F32_REFINE
             r = srv.acquire(n, dt, vectors=k % 5 != 4)
@@ -322,7 +335,7 @@ def test_a_tick_of_many_segments(source):
         st = srv.stats()
         print(f"  ticks {st['ticks']}, segments per tick at peak "
               f"{st['segments_per_tick_peak']}", flush=True)
-        assert st["segments_per_tick_peak"] > 128
+        assert st["segments_per_tick_peak"] > (512 if nreq > 512 else 128)
 
 
 def test_caller_may_drop_its_ready_event_right_after_submit(source):
