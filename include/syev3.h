@@ -248,16 +248,16 @@ int syev3_version(void);
  * free, and returns device pointers into the pool (SoA layout, ld = n).  The
  * client writes A (on any stream; it must be complete before submit) and
  * calls syev3_server_submit.  A scheduler thread gathers every submitted
- * request into the next tick: one launch of a persistent kernel that walks a
- * device table of the tick's requests (mixed dtypes) and solves them with the
+ * request into the next tick: one launch of a kernel that reads a device
+ * table of the tick's requests (mixed dtypes) and solves them with the
  * same per-matrix arithmetic as batched_syev3, so each result is bitwise the
  * same alone and in any mix.  Up to `max_inflight_ticks` ticks run at once on
  * separate streams, so requests that arrive while others are on the GPU start
  * without waiting for them.  Completion is detected by events; then
  * syev3_server_poll reports the request done and its outputs are readable.
  * syev3_server_release returns the request's memory to the pool, which admits
- * waiting requests.  Ticks are launched through HIP graphs captured once per
- * table slot.
+ * waiting requests.  A tick is the table's copy and the kernel, launched
+ * directly or (use_graphs) through a HIP graph captured once per tick slot.
  * ------------------------------------------------------------------------
  */
 typedef struct syev3_server syev3_server;

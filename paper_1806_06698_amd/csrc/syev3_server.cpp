@@ -5,9 +5,10 @@
 // list), fill its input on the device, and submit it.  A scheduler thread
 // forms ticks from everything submitted so far: a table of the requests
 // (segments) is written to pinned host memory and the tick is launched on
-// one of `max_inflight_ticks` streams, either as a graph captured once per
-// tick slot (copy of the table to the device, then the persistent segment
-// kernel) or as the same two operations issued directly.  While some ticks
+// one of `max_inflight_ticks` streams: the copy of the table to the device,
+// then the segment kernel with one workgroup per tile of the tick, issued
+// directly or (use_graphs) as a graph captured once per tick slot whose
+// kernel node's grid is set before each replay.  While some ticks
 // run, newly submitted requests go into the next free slot's tick, so work
 // of different ticks overlaps on the device.  Completion is observed by
 // polling each tick's event; results are then readable and the request can
@@ -342,8 +343,8 @@ int syev3_server::init(const syev3_server_opts& opts) {
   done_ids.reserve(o.max_requests);
   table_bytes = syev3::tick_table_bytes(o.max_segments_per_tick);
   // By default one workgroup per tile of each tick.  A workgroup that goes
-  // on to a second tile waits, before that tile's loads complete, for the
-  // first tile's stores as well (one counter tracks both), which one that
+  // on to a second tile likely waits, before that tile's loads complete, for
+  // the first tile's stores as well (one counter tracks both), which one that
   // ends after its stores never does: on a tick of 202 stress-mix requests
   // (16.8 M matrices) the kernel took 0.49 ms with one workgroup per tile
   // against 0.59 ms with 32 per compute unit striding over the tiles, and
