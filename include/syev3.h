@@ -309,8 +309,8 @@ typedef struct {
 
 /* Defaults: 64 GiB pool, 4096 slots, 4 ticks in flight, 256 segments/tick,
  * one workgroup per tile, graphs off (a tick is a table copy and one kernel;
- * launched directly these served the stress-mix load about 5% faster, and
- * about 15 us sooner at low load, than through a graph). */
+ * launched directly they complete 15-20 us sooner at low load than through a
+ * graph, and serve as many matrices per second at saturation). */
 void syev3_server_default_opts(syev3_server_opts* opts);
 
 /* Create a server on the current device.  Allocates the pool and starts the

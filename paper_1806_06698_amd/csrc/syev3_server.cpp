@@ -466,6 +466,8 @@ void syev3_server_default_opts(syev3_server_opts* o) {
   o->max_inflight_ticks = 4;
   o->max_segments_per_tick = 256;
   o->grid_blocks = 0;
+  // direct launches: 15-20 us sooner at low load than graph-launched ticks,
+  // the same throughput at saturation
   o->use_graphs = 0;
 }
 
