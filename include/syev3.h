@@ -414,7 +414,10 @@ int syev3_server_get_stats(syev3_server* s, syev3_server_stats* out);
  * call's contents (each call writes all of the table it reads).  Calls in
  * one stream's order are safe; calls that overlap on one GPU (on streams
  * not ordered with each other) race, and a kernel may then read a table
- * that another call has overwritten.
+ * that another call has overwritten.  The table's device address
+ * is looked up at the first call on each GPU and kept: after a
+ * hipDeviceReset of that GPU the call must not be used again in the
+ * process.
  *
  * Returns SYEV3_OK (nothing is enqueued when every n is 0); SYEV3_E_SEGMENTS
  * for nseg < 0 or nseg > SYEV3_SEGMENTS_MAX; SYEV3_E_NULL for segs == NULL
