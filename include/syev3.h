@@ -256,8 +256,9 @@ int syev3_version(void);
  * without waiting for them.  Completion is detected by events; then
  * syev3_server_poll reports the request done and its outputs are readable.
  * syev3_server_release returns the request's memory to the pool, which admits
- * waiting requests.  A tick is the table's copy and the kernel, launched
- * directly or (use_graphs) through a HIP graph captured once per tick slot.
+ * waiting requests.  A tick is the table's copy and the kernel, replayed
+ * from a HIP graph captured once per tick slot (use_graphs, the default) or
+ * launched directly.
  * ------------------------------------------------------------------------
  */
 typedef struct syev3_server syev3_server;
@@ -308,9 +309,9 @@ typedef struct {
 } syev3_server_stats;
 
 /* Defaults: 64 GiB pool, 4096 slots, 4 ticks in flight, 256 segments/tick,
- * one workgroup per tile, graphs off (a tick is a table copy and one kernel;
- * launched directly they complete 15-20 us sooner at low load than through a
- * graph, and serve as many matrices per second at saturation). */
+ * one workgroup per tile, graphs on (launched directly instead, the table
+ * copy and the kernel complete 15-20 us sooner at low load, with the same
+ * throughput at saturation). */
 void syev3_server_default_opts(syev3_server_opts* opts);
 
 /* Create a server on the current device.  Allocates the pool and starts the
