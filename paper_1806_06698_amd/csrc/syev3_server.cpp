@@ -165,12 +165,6 @@ Request* lookup(syev3_server* s, int64_t id, int* slot_out) {
   return r;
 }
 
-size_t request_bytes(int64_t n, int dtype, bool vecs) {
-  const size_t es = dtype == SYEV3_F64 ? 8 : 4;
-  return align_up(6 * (size_t)n * es) + align_up(3 * (size_t)n * es) +
-         (vecs ? align_up(9 * (size_t)n * es) : 0);
-}
-
 }  // namespace
 
 int syev3_server::launch_tick(int slot) {
