@@ -77,3 +77,15 @@ def test_soa_out_tensors_and_the_output_stride():
         s3._check_out_soa(torch.empty(n, 3, dtype=torch.float64).t(), 3, n, A, "lam")
     with pytest.raises(ValueError):
         s3._check_out_soa(torch.empty(3, n, dtype=torch.float32), 3, n, A, "lam")
+
+
+def test_segment_call_binding_checks_its_tensors():
+    """syev3_solve_segments_noalloc's binding: no segments is a no-op, and
+    host tensors are refused before anything reaches the library (the
+    kernels have no CPU path)."""
+    s3.syev3_solve_segments_noalloc([])
+    n = 8
+    A = torch.zeros(6, n, dtype=torch.float64)
+    lam = torch.empty(3, n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU"):
+        s3.syev3_solve_segments_noalloc([(A, lam, None)])
