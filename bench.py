@@ -60,6 +60,10 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run only a plain device copy of 2^30 bytes (known traffic), "
                         "to calibrate the FETCH_SIZE/WRITE_SIZE counters")
+    p.add_argument("--segments-probe", action="store_true",
+                   help="run only one serving tick's work, many stress-mix requests in one "
+                        "launch of the segment kernel, beside the batched kernels on the same "
+                        "matrices (for a profiler's kernel trace)")
     return p.parse_args()
 
 
@@ -70,6 +74,46 @@ def copy_calibration(torch):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_each_way": src.numel() * 8, "launches": 3}))
+
+
+def segments_probe(torch, s3, gen, launches=13):
+    """A serving tick's work without the server: requests of floor(2^U(0,20))
+    stress-mix matrices (alternately FP64 and FP32 storage, with vectors; up
+    to 2^24 matrices in all) solved in one launch of the segment kernel
+    through syev3_solve_segments_noalloc, `launches` times; then the batched
+    kernels on all 2^24 matrices of each form, as many times.  A profiler's
+    kernel trace gives the kernels' durations: the segment kernel against
+    the batched ones weighted by the requests' FP64 and FP32 shares."""
+    n = 1 << 24
+    A64, _ = gen.stress_mix(n, seed=3, device="cuda")
+    A32 = A64.float().contiguous()
+    g = torch.Generator().manual_seed(1)
+    segs, off, m64, m32 = [], 0, 0, 0
+    while len(segs) < 1024:
+        k = int(2 ** (20 * float(torch.rand(1, generator=g))))
+        if off + k > n:
+            break
+        f32 = len(segs) % 2 == 1
+        A = (A32 if f32 else A64)[:, off:off + k]
+        segs.append((A, torch.empty(3, k, dtype=A.dtype, device="cuda"),
+                     torch.empty(9, k, dtype=A.dtype, device="cuda")))
+        if f32:
+            m32 += k
+        else:
+            m64 += k
+        off += k
+    for _ in range(launches):
+        s3.syev3_solve_segments_noalloc(segs)
+    torch.cuda.synchronize()
+    for A in (A64, A32):
+        out = s3.syev3(A)
+        for _ in range(launches):
+            s3.syev3(A, out=out)
+    torch.cuda.synchronize()
+    print(json.dumps({"segments_probe": {"requests": len(segs), "matrices": off,
+                                         "fp64_share": m64 / off, "fp32_share": m32 / off,
+                                         "batched_matrices_per_form": n,
+                                         "launches_each": launches}}))
 
 
 def timed_launches(fn, steps, warmup, torch):
@@ -258,6 +302,9 @@ def main():
         return
     import paper_1806_06698_amd as s3
     from paper_1806_06698_amd import gen
+    if args.segments_probe:
+        segments_probe(torch, s3, gen)
+        return
 
     # The CPU baseline runs first, while the GPU is idle: the GPU timings then
     # start from an idle device, not from whatever ran just before this
