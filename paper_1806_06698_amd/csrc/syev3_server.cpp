@@ -342,8 +342,9 @@ int syev3_server::init(const syev3_server_opts& opts) {
   // ends after its stores never does: on a tick of 202 stress-mix requests
   // (16.8 M matrices) the kernel took 0.49 ms with one workgroup per tile
   // against 0.59 ms with 32 per compute unit striding over the tiles, and
-  // the serving load (input views, 256 requests in flight) served 35.9
-  // against 33.0 G matrices/s with a fixed 32768 workgroups.  A fixed grid
+  // the serving load (input views, 256 requests in flight) served 35.9 G
+  // matrices/s with a fixed 32768 workgroups against 33.0 with 8192 (32
+  // per compute unit).  A fixed grid
   // far above the tiles costs latency instead (workgroups with no tile:
   // p50 at 2000 requests/s 0.07 ms with 131072, 0.15 ms with 524288), so
   // the grid is sized per tick.
