@@ -366,41 +366,67 @@ hipError_t launch_batched(int64_t n, const void* A, Strides ld, int layout,
 // One tile of segment s: matrices t0 .. t0 + kBlock - 1.  The tile's first
 // matrix is folded into the plane bases (uniform, in scalar registers), so
 // each lane adds only threadIdx.x elements as a 32-bit byte offset, whatever
-// the request's size; the stores again see it as 32-bit past the solve (the
-// empty asm re-defines it), so no 64-bit address is formed per access, as in
-// the batched SoA kernel.  Every tile solves for vectors, and a request
+// the request's size: every load and store of the solve is a global access
+// of a scalar base and that offset, as in the batched SoA kernel (empty asm
+// statements keep the bases scalar and the offset 32-bit; only the NaN path
+// forms full addresses).  Every tile solves for vectors, and a request
 // without them (V null, a uniform branch) skips only their stores: with one
 // solve per form the kernel holds two inlined solves, not four, and fits in
-// 60 VGPRs (8 waves per SIMD; four solves needed 84, 5 waves).
+// 62 VGPRs (8 waves per SIMD; four solves needed 84, 5 waves).
 template <int FORM>
 __device__ __forceinline__ void solve_segment_tile(const Segment& s, int64_t t0) {
   using T = Storage<FORM>;
+  // the table's pointers are generic: cast to global memory, else every
+  // access is a flat one with a 64-bit address per lane
+  using GT = __attribute__((address_space(1))) T;
+  using GC = __attribute__((address_space(1))) char;
   const int64_t pa = s.lda * (int64_t)sizeof(T), po = s.n * (int64_t)sizeof(T);
-  const char* A = (const char*)s.A + t0 * (int64_t)sizeof(T);
-  char* L = (char*)s.lambda + t0 * (int64_t)sizeof(T);
-  char* W = (char*)s.V + t0 * (int64_t)sizeof(T);
+  const GC* A = (const GC*)s.A + t0 * (int64_t)sizeof(T);
+  GC* L = (GC*)s.lambda + t0 * (int64_t)sizeof(T);
+  GC* W = (GC*)s.V + t0 * (int64_t)sizeof(T);
   const bool vecs = s.V != nullptr;
-  const uint32_t off = threadIdx.x * (uint32_t)sizeof(T);
+  uint32_t off = threadIdx.x * (uint32_t)sizeof(T);
+  asm volatile("" : "+v"(off));
   double a[6];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) a[k] = (double)ld_stream((const T*)(A + k * pa + off));
+  for (int k = 0; k < 6; ++k) {
+    // each plane's base pinned in scalar registers (else the compiler chains
+    // the planes' addresses per lane in 64 bits)
+    const GC* p = A + k * pa;
+    asm volatile("" : "+s"(p));
+    a[k] = (double)__builtin_nontemporal_load((const GT*)(p + off));
+  }
   double l[3], v[9];
   bool bad;
   solve3<true, FORM>(a, s.flags, l, v, bad);
   uint32_t soff = off;
   asm volatile("" : "+v"(soff));
+  GC* lp[3];
+  GC* vp[9];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) st_stream((T)l[j], (T*)(L + j * po + soff));
+  for (int j = 0; j < 3; ++j) {
+    lp[j] = L + j * po;
+    asm volatile("" : "+s"(lp[j]));
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    vp[k] = W + k * po;
+    asm volatile("" : "+s"(vp[k]));
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) __builtin_nontemporal_store((T)l[j], (GT*)(lp[j] + soff));
   if (vecs) {
+    uint32_t voff = soff;
+    asm volatile("" : "+v"(voff));
 #pragma unroll
-    for (int k = 0; k < 9; ++k) st_stream((T)v[k], (T*)(W + k * po + soff));
+    for (int k = 0; k < 9; ++k) __builtin_nontemporal_store((T)v[k], (GT*)(vp[k] + voff));
   }
   if (bad) {  // a NaN or infinite entry: NaN in every output of the matrix
 #pragma unroll
-    for (int j = 0; j < 3; ++j) st_stream(qnan<T>(), (T*)(L + j * po + soff));
+    for (int j = 0; j < 3; ++j) __builtin_nontemporal_store(qnan<T>(), (GT*)(lp[j] + soff));
     if (vecs) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) st_stream(qnan<T>(), (T*)(W + k * po + soff));
+      for (int k = 0; k < 9; ++k) __builtin_nontemporal_store(qnan<T>(), (GT*)(vp[k] + soff));
     }
   }
 }
