@@ -423,3 +423,41 @@ def test_loadgen_with_input_views(source):
                           seed=5, input_views=True)
     print(res, flush=True)
     assert res["requests"] > 32 and 0 < res["lat_p50_s"] <= res["lat_p99_s"]
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_non_finite_inputs_in_served_requests(source, use_graphs):
+    """Requests whose inputs hold NaN and infinite entries in some matrices,
+    in both forms, with and without vectors: exactly those matrices come out
+    NaN (every eigenvalue and vector entry), and every output equals a
+    separate batched solve bit for bit (the serving kernel's NaN stores
+    included)."""
+    A64, A32 = source
+    specs = [(1000, s3.F64, True), (777, s3.F32_REFINE, True), (300, s3.F64, False),
+             (2049, s3.F32_REFINE, False)]
+    with serve.Server(hbm_budget_bytes=1 << 30, use_graphs=use_graphs) as srv:
+        reqs = []
+        for k, (n, dt, vec) in enumerate(specs):
+            r = srv.acquire(n, dt, vectors=vec)
+            src = (A64 if dt == s3.F64 else A32)[:, 5000 * k:5000 * k + n].clone()
+            bad = (torch.arange(n, device="cuda") % 97) == 3
+            cols = bad.nonzero().flatten()
+            for i, c in enumerate(cols.tolist()):
+                src[i % 6, c] = (float("nan"), float("inf"), float("-inf"))[i % 3]
+            r.A.copy_(src)
+            ev = torch.cuda.Event()
+            ev.record()
+            srv.submit(r, ev)
+            reqs.append((r, bad))
+        for r, bad in reqs:
+            srv.wait(r, timeout_s=60.0)
+            lam, V = s3.syev3(r.A.clone(), vectors=r.V is not None)
+            torch.cuda.synchronize()
+            ib = torch.int64 if lam.dtype == torch.float64 else torch.int32
+            assert torch.equal(lam.view(ib), r.lam.view(ib)), f"lambda differs for n={r.n}"
+            assert torch.isnan(r.lam[:, bad]).all() and torch.isfinite(r.lam[:, ~bad]).all()
+            if V is not None:
+                assert torch.equal(V.view(ib), r.V.view(ib)), f"V differs for n={r.n}"
+                assert torch.isnan(r.V[:, bad]).all() and torch.isfinite(r.V[:, ~bad]).all()
+            srv.release(r)
+        assert srv.stats()["pool_bytes_in_use"] == 0
